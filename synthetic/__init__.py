@@ -1,0 +1,8 @@
+"""Seeded synthetic inputs (plane-wave basis, orbital energies, orbital
+coefficients) shared by the CPU oracle and the GPU path.  No MP2 arithmetic
+lives here."""
+from .model import (CellSpec, C1, C2, C3, orbital_miller, make_cell,
+                    random_unitary, tiny_spec, hamiltonian)
+
+__all__ = ["CellSpec", "C1", "C2", "C3", "orbital_miller", "make_cell",
+           "random_unitary", "tiny_spec", "hamiltonian"]
