@@ -1,0 +1,178 @@
+"""Throughput of the Gamma-only LTMP2 hot path on one MI355X.
+
+One step = one full energy E = E_d + E_x of one cell over all Laplace points
+(every kernel of the path: Green's-function tiles + chi transforms + Coulomb
+trace, and the transformed-state GEMM + synthesis + Fock-like pair
+transforms), inputs resident in HBM.  Setup (orbital synthesis, overlap
+densities, quadrature fit) is outside the timed region.
+
+Prints one JSON line (rank 0).  Extra objects:
+  roofline      dominant kernel stage: algorithmic work per launch divided
+                by its mean event-timed duration, against the MI355X peak
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cell,
+                scaled to energies / s
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12      # FP64 vector and matrix, FLOP/s
+PEAK_HBM = 8.0e12        # bytes/s
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from synthetic import C1, C2, C3
+    return {"c1": C1, "c2": C2, "c3": C3}[name]
+
+
+def stage_work(info, n, stage):
+    """Algorithmic (flops, bytes) of one energy for a timing stage."""
+    nr, ng, nh, no, nv, npw, nt = (info.n_r, info.n_g, info.n_h, info.n_occ, info.n_vir,
+                                   info.n_pw, info.n_tau)
+    lg = math.log2(nr)
+    if stage == "chi_tiles":      # symmetric real GEMMs, upper triangle only
+        return nt * nr * nr * (no + nv) * 1.0, None
+    if stage == "w_gemm":         # complex C x real basis, G' in H
+        return nt * 4.0 * nh * no * nv * npw, None
+    if stage == "pair":           # N_o^2 complex 3-D FFTs per outer G' (H and -H)
+        return nt * ng * no * no * 5.0 * nr * lg / 2.0 * 1.0, None
+    if stage == "chi_rows":       # read chi rows once
+        return None, nt * 8.0 * nr * nr
+    if stage == "chi_cols":
+        return None, nt * 16.0 * nh * nr
+    if stage == "w_synth":
+        return nt * nh * no * 5.0 * nr * lg, None
+    return None, None
+
+
+def cpu_baseline(spec, m, e, c, budget_s=25.0):
+    """FP64 oracle on one occupied orbital of the same cell, scaled up.
+
+    Sample: Laplace MP2 restricted to the occupied subset {HOMO}: overlap
+    densities of that orbital with every virtual (both orderings) and the
+    one (i, j) pair's integrals and Laplace sums.  The full energy needs
+    N_occ times the density work and N_occ^2 times the pair work.
+    """
+    import numpy as np
+    from oracle.mp2 import Problem
+    from oracle.quadrature import minimax_laplace
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    P = Problem(spec.L, spec.n, spec.eaux, m, e, c, spec.n_occ, occ=[spec.n_occ - 1])
+    tau, w, _ = minimax_laplace(*P.x_range(), spec.n_tau)
+    t0 = time.perf_counter()
+    _ = P.psi_o, P.psi_v
+    t1 = time.perf_counter()
+    _ = P.n_ov, P.n_vo
+    t2 = time.perf_counter()
+    P.energies(tau, w)
+    t3 = time.perf_counter()
+    no = spec.n_occ
+    full = (t1 - t0) * (spec.n_occ + 0) / 1.0 + (t2 - t1) * no + (t3 - t2) * no * no
+    return {"value": 1.0 / full, "unit": "energies/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle LT-MP2 for occupied subset {{HOMO}} of the {spec.n}^3 cell "
+                      f"(orbitals {t1 - t0:.1f}s, pair densities {t2 - t1:.1f}s, "
+                      f"one pair {t3 - t2:.1f}s); full energy = orbitals + "
+                      f"{no} x densities + {no}^2 x pair = {full:.0f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from synthetic import make_cell
+    from paper_1611_06797_amd import Context
+
+    spec = workload(args.config)
+    log("workload", spec)
+    t = time.time()
+    m, e, c = make_cell(spec)
+    log(f"cell ready ({time.time() - t:.1f}s): n_pw={m.shape[0]}")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t = time.time()
+    ctx = Context(spec.L, spec.n, spec.ecut, spec.eaux, m, e, c, spec.n_occ, spec.n_tau,
+                  stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    info = ctx.info
+    log(f"setup {time.time() - t:.1f}s: n_g={info.n_g} n_vir={info.n_vir} "
+        f"device {info.device_bytes / 2**30:.1f} GiB quad_delta={info.quad_delta:.3e}")
+    for k in range(args.warmup):
+        t = time.time()
+        ctx.energy()
+        log(f"warmup {k}: {time.time() - t:.2f}s")
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ed, ex, pt, qe = ctx.energy()
+        log(f"step {k}: E_d={ed:.10f} E_x={ex:.10f}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    timing = ctx.get_timing()
+    ms_step = 1000.0 * dt / args.steps
+    log("stage ms per step:", {k: round(v[0] / args.steps, 2) for k, v in timing.items()})
+
+    # dominant kernel stage and its roofline
+    dom = max(timing, key=lambda k: timing[k][0])
+    ms_tot, launches = timing[dom]
+    flops, byts = stage_work(info, spec.n, dom)
+    per_launch_s = ms_tot / 1000.0 / max(launches, 1)
+    if flops is not None:
+        per_launch = flops * args.steps / max(launches, 1)
+        ach = per_launch / per_launch_s
+        roof = {"bound": "alu" if dom == "pair" else "mfma", "achieved": ach / 1e12,
+                "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
+                "traffic": None}
+    else:
+        per_launch = byts * args.steps / max(launches, 1)
+        ach = per_launch / per_launch_s
+        roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": ach / PEAK_HBM, "traffic": None}
+    roof["kernel"] = dom
+    roof["launches_per_step"] = launches / args.steps
+    roof["mean_launch_ms"] = 1000.0 * per_launch_s
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)...")
+        cpu = cpu_baseline(spec, m, e, c)
+    out = {"metric": "LTMP2 energies/sec", "value": args.steps / dt, "unit": "energies/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"gamma-only LTMP2 cell L={spec.L} bohr, {spec.n}^3 grid, "
+                                  f"E_cut={spec.ecut} Ha (n_pw={info.n_pw}), "
+                                  f"E_aux={spec.eaux} Ha (n_g={info.n_g}), "
+                                  f"n_occ={spec.n_occ}, n_tau={spec.n_tau}, seed={spec.seed}",
+                      "precision": "fp64", "quadrature": "plain minimax"},
+           "energy": {"e_direct": ed, "e_exchange": ex, "quad_delta": qe},
+           "stage_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
+           "roofline": roof, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

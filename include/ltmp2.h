@@ -1,0 +1,206 @@
+/*
+ * libltmp2 -- Gamma-only Laplace-transformed MP2 (LTMP2) on one MI355X.
+ *
+ * C ABI over the hot path of the quartic-scaling plane-wave LTMP2 method of
+ * Schaefer, Ramberger and Kresse ("Quartic scaling MP2 for solids",
+ * arXiv:1611.06797).  Given Hartree-Fock orbitals and energies for all
+ * occupied and virtual states (the inputs the paper's Implementation section
+ * assumes), the library returns the direct and exchange MP2 correlation
+ * energies of a spin-restricted closed-shell cell:
+ *
+ *   E_d = -2 sum_n w_n Tr[(chi(tau_n) v)^2]                (Eq. dLTMP2Compact, q = 0)
+ *   E_x =    sum_n w_n sum_{G,G'} v(G) v(G') sum_ij A^{G'}_ij(G) A^{-G'}_ji(-G)
+ *                                                          (Eqs. SCHnewstate,
+ *                                                           SCHtransmatrix, SCHfocklike)
+ * with v(G) = 4 pi / (Omega |G|^2) on the auxiliary set (Eq. SCH2EI), the
+ * Laplace transform of the energy denominator (Eq. SCHLT) and a minimax
+ * quadrature (tau_n, w_n).
+ *
+ * Conventions (Hartree atomic units):
+ *   - cubic cell of side L (bohr), Omega = L^3, FFT grid n^3, dV = Omega / n^3;
+ *   - reciprocal vectors G = (2 pi / L) m with integer Miller indices m;
+ *   - orbitals psi_p(r) = Omega^-1/2 sum_G c_p(G) e^{iG.r} must be real on the
+ *     grid (Gamma point, time-reversal symmetry: c_p(-G) = conj c_p(G));
+ *   - auxiliary set: G != 0 with |G|^2 / 2 <= eaux, |m_d| < n / 2;
+ *   - real-space index used by device outputs: r = (x * n + z) * n + y
+ *     for grid point (x, y, z) (z varies before y).
+ *
+ * Ownership: host inputs are copied during the call; device output buffers
+ * are allocated by the caller and written on the context's stream; every
+ * device allocation made by the library belongs to the context and is
+ * released by ltmp2_destroy.  Calls return a status and never abort; a text
+ * message is available from ltmp2_last_error.  After a device error the
+ * context is failed and later calls return LTMP2_ESTATE.  A context must
+ * not be used from two threads at once.
+ */
+#ifndef LTMP2_H
+#define LTMP2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ltmp2_ctx ltmp2_ctx;
+
+typedef enum {
+  LTMP2_OK = 0,
+  LTMP2_EINVAL = 1,   /* invalid argument or input data                    */
+  LTMP2_EGAP = 2,     /* e_LUMO - e_HOMO <= 1e-8 Ha: the Laplace transform of
+                         1/D needs e_i < e_F < e_a (LTMP2 subsection)        */
+  LTMP2_ENOMEM = 3,   /* device memory (or the workspace cap) exhausted     */
+  LTMP2_EDEVICE = 4,  /* HIP runtime error                                  */
+  LTMP2_ESTATE = 5,   /* call on a failed context or out of order           */
+  LTMP2_ENUMERIC = 6  /* quadrature fit failed / non-finite result          */
+} ltmp2_status;
+
+typedef enum {
+  LTMP2_FP64 = 0,     /* FP64 throughout                                    */
+  LTMP2_FP32 = 1,     /* FP32 storage and transforms; FP64 accumulations    */
+  LTMP2_BF16X3 = 2    /* split-BF16x3 Green's-function GEMMs, FP32 otherwise */
+} ltmp2_precision;
+
+typedef enum {
+  LTMP2_QUAD_PLAIN = 0,   /* library computes the minimax fit               */
+  LTMP2_QUAD_LEARNED = 1, /* MLP proposal + Remez polish + certified judge  */
+  LTMP2_QUAD_GIVEN = 2    /* caller passes tau and w                         */
+} ltmp2_quad_mode;
+
+typedef struct {
+  double L;             /* cubic cell side, bohr (> 0)                          */
+  int n_fft;            /* grid points per axis; one of the compiled sizes     */
+  double ecut;          /* orbital cutoff, Ha: every basis G has |G|^2/2 < ecut */
+  double eaux;          /* auxiliary cutoff, Ha (inclusive)                     */
+  int n_pw;             /* basis size = number of states (all virtuals kept)    */
+  int n_occ;            /* occupied states, 1 <= n_occ < n_pw                   */
+  int n_tau;            /* Laplace points, 1..16                                */
+  int quad_mode;        /* ltmp2_quad_mode                                      */
+  int prec;             /* ltmp2_precision                                      */
+  size_t workspace_cap; /* bytes; 0 = no cap.  Setup fails with LTMP2_ENOMEM if
+                           the device footprint would exceed it                 */
+} ltmp2_params;
+
+/* Sizes of a prepared context. */
+typedef struct {
+  int n_r;        /* n^3                                                  */
+  int n_g;        /* auxiliary set size (G and -G both counted)           */
+  int n_h;        /* n_g / 2: the half set, first in the library's order  */
+  int n_pw, n_occ, n_vir, n_tau;
+  double x_min, x_max;   /* bounds of -D = e_a + e_b - e_i - e_j          */
+  double quad_delta;     /* certified max relative quadrature error       */
+  size_t device_bytes;   /* device memory held by the context             */
+} ltmp2_info;
+
+/*
+ * Prepare a cell (Implementation section, step (i)): validates all inputs on
+ * the host before any device call, uploads them, synthesises the orbitals on
+ * the grid, computes and stores the overlap densities <a|e^{-iG.r}|j>
+ * (Eq. SCHovrlp) and fixes the Laplace quadrature.
+ *   miller [n_pw][3] int32   basis Miller indices (closed under m -> -m)
+ *   eps    [n_pw]            orbital energies, ascending
+ *   coeff  [n_pw][n_pw][2]   state-major coefficients c_p(G), (re, im)
+ *   tau, w [n_tau]           quadrature (only with LTMP2_QUAD_GIVEN, else NULL)
+ *   mlp_weights              path of a weight file (LTMP2_QUAD_LEARNED), else NULL
+ *   hip_stream               hipStream_t to run on (NULL: default stream)
+ * On success *out receives a context; on failure *out is NULL.
+ */
+ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller, const double* eps,
+                         const double* coeff, const double* tau, const double* w,
+                         const char* mlp_weights, void* hip_stream, ltmp2_ctx** out);
+
+/*
+ * Occupied and virtual imaginary-time Green's functions at tau_itau
+ * (spec G_occ / G_vir; the occupied and virtual sums of
+ * Eq. dLTMP2Compact), rows [row0, row0 + nrows) of the n_r x n_r matrices
+ *   G_occ(r, r') = sum_i psi_i(r) exp((e_i - mu) tau) psi_i(r')
+ *   G_vir(r, r') = sum_a psi_a(r) exp(-(e_a - mu) tau) psi_a(r')
+ * with mu = (e_HOMO + e_LUMO) / 2, written as doubles [nrows][n_r] to the
+ * caller's device buffers (either may be NULL).  Diagnostic entry point.
+ */
+ltmp2_status ltmp2_green(ltmp2_ctx* ctx, int itau, int row0, int nrows, void* gocc_dev,
+                         void* gvir_dev);
+
+/*
+ * Direct term at tau_itau: chi(r, r') = G_occ(r, r') G_vir(r', r) tile by
+ * tile, its double Fourier transform
+ *   chi(G, G') = dV^2 sum_{r, r'} e^{-iG.r} chi(r, r') e^{iG'.r'}
+ * on the auxiliary set and the Coulomb trace
+ *   *e_direct_tau = -2 sum_{G, G'} v(G) v(G') |chi(G, G')|^2   (unweighted).
+ * chi_GG_dev (may be NULL) receives chi(G, G') as complex doubles
+ * [n_g][n_g] in the library's auxiliary order (ltmp2_aux_miller).
+ */
+ltmp2_status ltmp2_chi(ltmp2_ctx* ctx, int itau, void* chi_GG_dev, double* e_direct_tau);
+
+/*
+ * Exchange term at tau_itau through the transformed states of
+ * Eqs. SCHnewstate / SCHtransmatrix and the Fock-like contraction of
+ * Eq. SCHfocklike (Implementation section, steps (iii) and (iv.b)):
+ *   *e_exchange_tau = sum_{G'} v(G') sum_G v(G) sum_ij A^{G'}_ij(G) A^{-G'}_ji(-G)
+ * (unweighted).  g_first / g_count select a range of the half set H of
+ * outer G' (g_count <= 0: all); the value then covers G' and -G' of that
+ * range only, so disjoint ranges add up to the full term.
+ */
+ltmp2_status ltmp2_exchange(ltmp2_ctx* ctx, int itau, int g_first, int g_count,
+                            double* e_exchange_tau);
+
+/*
+ * Full energy: E_d = sum_n w_n E_d(tau_n), E_x = sum_n w_n E_x(tau_n)
+ * (Ha per cell).  per_tau (may be NULL) receives [2 n_tau] unweighted values
+ * (E_d(tau_n), E_x(tau_n)) pairs; quad_err (may be NULL) the certified max
+ * relative error of the quadrature.
+ */
+ltmp2_status ltmp2_energy(ltmp2_ctx* ctx, double* e_direct, double* e_exchange,
+                          double* per_tau, double* quad_err);
+
+/* Quadrature in use: tau, w [n_tau] (host), may be NULL. */
+ltmp2_status ltmp2_get_quadrature(const ltmp2_ctx* ctx, double* tau, double* w, double* delta);
+
+/* Sizes of the context. */
+ltmp2_status ltmp2_get_info(const ltmp2_ctx* ctx, ltmp2_info* info);
+
+/* Miller indices of the auxiliary set in the library's order, [n_g][3]
+ * (half set H first, then -H in the same order). */
+ltmp2_status ltmp2_aux_miller(const ltmp2_ctx* ctx, int32_t* out);
+
+/*
+ * Host-only relative-error minimax Laplace quadrature for 1/x on
+ * [x_min, x_max] (Eq. SCHLT evaluated by a quadrature, LTMP2 subsection):
+ * minimises max |x sum_n w_n e^{-x tau_n} - 1| by Remez exchange with
+ * continuation in R = x_max / x_min.  For n_tau >= 9 the fit is computed on
+ * [x_min, x_min * max(R, R_floor)], R_floor = exp(0.5 (n_tau - 10) + 3.8),
+ * the double-precision limit of the exchange.  tau, w [n_tau] ascending in
+ * tau; delta = certified max relative error.  Touches no device.
+ */
+ltmp2_status ltmp2_quadrature(double x_min, double x_max, int n_tau, double* tau, double* w,
+                              double* delta);
+
+/*
+ * Per-stage device timing (diagnostics for roofline accounting).  When on,
+ * every kernel launch of the hot path is bracketed by HIP events on the
+ * context's stream; ltmp2_get_timing synchronises the stream and returns the
+ * summed milliseconds and launch count of one stage:
+ *   0 chi tiles (G_occ / G_vir GEMMs + Hadamard), 1 chi row transforms,
+ *   2 chi column transforms + Coulomb trace, 3 transformed-state GEMM,
+ *   4 transformed-state synthesis, 5 Fock-like pair transforms, 6 reductions.
+ * ltmp2_set_timing(ctx, 1) also clears the accumulated values.
+ */
+ltmp2_status ltmp2_set_timing(ltmp2_ctx* ctx, int on);
+ltmp2_status ltmp2_get_timing(ltmp2_ctx* ctx, int stage, double* ms, long* launches);
+
+/* Release a context and all of its device memory (NULL is ignored). */
+void ltmp2_destroy(ltmp2_ctx* ctx);
+
+/* Message of the last error on ctx (or of the last failed setup if ctx is
+ * NULL).  Valid until the next call on the same context. */
+const char* ltmp2_last_error(const ltmp2_ctx* ctx);
+
+/* Compiled grid sizes: writes up to cap values to sizes, returns the count. */
+int ltmp2_supported_grids(int* sizes, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LTMP2_H */

@@ -1,0 +1,276 @@
+// Transform kernels of the LTMP2 path (templated on precision T and grid n).
+#pragma once
+#include "transforms.hpp"
+
+namespace ltmp2 {
+
+struct SphereCols {
+  int ncol;
+  int kmax;
+  const int* cdesc;   // [ncol]
+  const int* cstart;  // [ncol + 1]
+  const int* ckx;     // [n_pw]
+};
+
+// ---------------------------------------------------------------------------
+// Orbitals on the grid: psi_p(r) = Omega^-1/2 sum_G c_p(G) e^{iG.r}, real for
+// time-reversal-invariant coefficients (Gamma point).
+//   coef: [n_items][n_pw] complex, entries in column order of the sphere
+//   psi:  [n_items][ld] real
+template <class T, int N>
+__global__ __launch_bounds__(kThreads) void k_orbitals(const cplx<double>* __restrict__ coef, int npw,
+                                                       SphereCols sc, int sx, double scale,
+                                                       T* __restrict__ psi, long ld) {
+  extern __shared__ __align__(16) char smem[];
+  const int nk = 2 * sc.kmax + 1;
+  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  fill_twiddles<T, 1>(L.tw, N);
+  for (int e = threadIdx.x; e < sx * nk * nk; e += kThreads) L.t2[e] = {T(0), T(0)};
+  __syncthreads();
+  const long p = blockIdx.x;
+  const cplx<double>* c = coef + p * npw;
+  T* out = psi + p * ld;
+  auto cf = [&](int, int e) { return cplx<T>{T(c[e].x), T(c[e].y)}; };
+  auto st = [&](int, int x, int y, int z, cplx<T> v) { out[(x * N + z) * N + y] = T(scale) * v.x; };
+  inverse_sphere<T, N, 1>(cf, st, 1, sc.kmax, sx, sc.ncol, sc.cdesc, sc.cstart, sc.ckx, L);
+}
+
+// ---------------------------------------------------------------------------
+// Overlap densities (step (i)): n_aj(G) = dV sum_r psi_a(r) psi_j(r) e^{-iG.r}
+// for G in the half set H.  Block (jblock, a); NF occupied j per block.
+//   nd: [n_vir][n_h][n_occ] complex
+template <class T, int N, int NF, int OPT>
+__global__ __launch_bounds__(kThreads) void k_overlap(const T* __restrict__ psi, long ld, int nocc,
+                                                      const int* __restrict__ gdesc_all, int nh,
+                                                      int kmax, int sx, double dV,
+                                                      cplx<T>* __restrict__ nd) {
+  extern __shared__ __align__(16) char smem[];
+  const int nk = 2 * kmax + 1;
+  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  fill_twiddles<T, -1>(L.tw, N);
+  const int j0 = blockIdx.x * NF;
+  const int a = blockIdx.y;
+  const int nf = min(NF, nocc - j0);
+  const T* pa = psi + long(nocc + a) * ld;
+  const T* pj = psi + long(j0) * ld;
+  int gd[OPT];
+  cplx<T> acc[NF][OPT];
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    gd[t] = (o < nh) ? gdesc_all[o] : 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f][t] = {T(0), T(0)};
+  }
+  __syncthreads();
+  auto ld_ = [&](int f, int x, int y, int z) {
+    const long r = (x * N + z) * N + y;
+    return cplx<T>{pa[r] * pj[f * ld + r], T(0)};
+  };
+  forward_pruned<T, -1, N, NF, OPT>(ld_, nf, kmax, sx, gd, nh, acc, L);
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    if (o < nh) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        if (f < nf)
+          nd[(long(a) * nh + o) * nocc + j0 + f] = {T(dV) * acc[f][t].x, T(dV) * acc[f][t].y};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First pass of the double transform of chi (rows): for NF rows r,
+//   chihat(r, G') = dV sum_r' chi(r, r') e^{+iG'.r'},  G' in H.
+//   chi: [n_r][ld] real;  chihat: [n_h][ld] complex (column-major in r)
+template <class T, int N, int NF, int OPT>
+__global__ __launch_bounds__(kThreads) void k_chi_rows(const T* __restrict__ chi, long ld, int nr,
+                                                       const int* __restrict__ gdesc_all, int nh,
+                                                       int kmax, int sx, double dV,
+                                                       cplx<T>* __restrict__ chihat) {
+  extern __shared__ __align__(16) char smem[];
+  const int nk = 2 * kmax + 1;
+  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  fill_twiddles<T, 1>(L.tw, N);
+  const int r0 = blockIdx.x * NF;
+  const int nf = min(NF, nr - r0);
+  const T* row = chi + long(r0) * ld;
+  int gd[OPT];
+  cplx<T> acc[NF][OPT];
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    gd[t] = (o < nh) ? gdesc_all[o] : 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f][t] = {T(0), T(0)};
+  }
+  __syncthreads();
+  auto ld_ = [&](int f, int x, int y, int z) {
+    return cplx<T>{row[f * ld + (x * N + z) * N + y], T(0)};
+  };
+  forward_pruned<T, 1, N, NF, OPT>(ld_, nf, kmax, sx, gd, nh, acc, L);
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    if (o < nh) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        if (f < nf) chihat[long(o) * ld + r0 + f] = {T(dV) * acc[f][t].x, T(dV) * acc[f][t].y};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Second pass (columns) and the Coulomb trace: for G' = H[g],
+//   chi(G, G') = dV sum_r e^{-iG.r} chihat(r, G'),  G in the full set,
+//   pd[g] = v(G') sum_G v(G) |chi(G, G')|^2.
+// Optionally stores chi(G, G') for G' in H and, by chi(-G, -G') =
+// conj chi(G, G') (real chi(r, r')), for G' in -H:  out[G][G'] (ng x ng).
+template <class T, int N, int OPT>
+__global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict__ chihat, long ld,
+                                                       const int* __restrict__ gdesc_all, int ng,
+                                                       int nh, const double* __restrict__ v,
+                                                       int kmax, int sx, double dV,
+                                                       double* __restrict__ pd,
+                                                       cplx<double>* __restrict__ chi_out) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double red[kThreads / 64];
+  const int nk = 2 * kmax + 1;
+  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  fill_twiddles<T, -1>(L.tw, N);
+  const int g = blockIdx.x;
+  const cplx<T>* col = chihat + long(g) * ld;
+  int gd[OPT];
+  cplx<T> acc[1][OPT];
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    gd[t] = (o < ng) ? gdesc_all[o] : 0;
+    acc[0][t] = {T(0), T(0)};
+  }
+  __syncthreads();
+  auto ld_ = [&](int, int x, int y, int z) { return col[(x * N + z) * N + y]; };
+  forward_pruned<T, -1, N, 1, OPT>(ld_, 1, kmax, sx, gd, ng, acc, L);
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    if (o < ng) {
+      const double re = dV * double(acc[0][t].x), im = dV * double(acc[0][t].y);
+      s += v[o] * (re * re + im * im);
+      if (chi_out) {
+        const int on = (o < nh) ? o + nh : o - nh;
+        chi_out[long(o) * ng + g] = {re, im};
+        chi_out[long(on) * ng + g + nh] = {re, -im};
+      }
+    }
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) pd[g] = v[g] * s;
+}
+
+// ---------------------------------------------------------------------------
+// Transformed states on the grid (step (iii)):
+//   w_j^{(G')}(r) = Omega^-1/2 sum_G W_j(G) e^{iG.r},
+// with W_j(G) rebuilt from the real-basis product P = C Psi_v:
+//   P[(g, j, 0)][q] = sum_a Re C_ja B[a][q],  P[(g, j, 1)][q] = sum_a Im C_ja B[a][q],
+// where B[a][q] holds Re c_a(0), Re c_a(G_k), Im c_a(G_k) for the half sphere.
+// Entry e of the sphere (column order) uses wq[e] = q_re | (q_im + 1) << 16
+// and the sign s = +1 for G_k, -1 for -G_k (c_a(-G) = conj c_a(G)):
+//   W(G) = (P_re[q_re] - s P_im[q_im]) + i (P_im[q_re] + s P_re[q_im]).
+template <class T, int N>
+__global__ __launch_bounds__(kThreads) void k_wstates(const double* __restrict__ P, int npw,
+                                                      const int* __restrict__ wq,
+                                                      const signed char* __restrict__ wsgn,
+                                                      SphereCols sc, int sx, double scale,
+                                                      cplx<T>* __restrict__ w, long ld) {
+  extern __shared__ __align__(16) char smem[];
+  const int nk = 2 * sc.kmax + 1;
+  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  fill_twiddles<T, 1>(L.tw, N);
+  for (int e = threadIdx.x; e < sx * nk * nk; e += kThreads) L.t2[e] = {T(0), T(0)};
+  __syncthreads();
+  const long item = blockIdx.x;
+  const double* pre = P + (2 * item) * long(npw);
+  const double* pim = pre + npw;
+  cplx<T>* out = w + item * ld;
+  auto cf = [&](int, int e) {
+    const int q = wq[e];
+    const int qr = q & 0xffff, qi = (q >> 16) - 1;
+    const double s = wsgn[e];
+    double re = pre[qr], im = pim[qr];
+    if (qi >= 0) {
+      re -= s * pim[qi];
+      im += s * pre[qi];
+    }
+    return cplx<T>{T(re), T(im)};
+  };
+  auto st = [&](int, int x, int y, int z, cplx<T> v) {
+    out[(x * N + z) * N + y] = {T(scale) * v.x, T(scale) * v.y};
+  };
+  inverse_sphere<T, N, 1>(cf, st, 1, sc.kmax, sx, sc.ncol, sc.cdesc, sc.cstart, sc.ckx, L);
+}
+
+// ---------------------------------------------------------------------------
+// Fock-like contraction (step (iv.b)) for one G' and one occupied pair i <= j:
+//   A_ij(G) = dV sum_r psi_i(r) w_j(r) e^{-iG.r},  G in the full set,
+//   xpart = sum_G v(G) [A_ij conj(A_ji) + A_ji conj(A_ij)]   (i < j)
+//         = sum_G v(G) |A_ii|^2                               (i = j).
+// Summed over pairs this is S_x(G') = sum_G v(G) sum_ij A_ij(G) A^{(-G')}_ji(-G),
+// using A^{(-G')}_ji(-G) = conj A^{(G')}_ji(G) for real orbitals.
+template <class T, int N, int OPT>
+__global__ __launch_bounds__(kThreads) void k_pair(const T* __restrict__ psi, long ld,
+                                                   const cplx<T>* __restrict__ w, int nocc,
+                                                   const int* __restrict__ pairs, int npairs,
+                                                   const int* __restrict__ gdesc_all, int ng,
+                                                   const double* __restrict__ v, int kmax, int sx,
+                                                   double dV2, double* __restrict__ xpart) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double red[kThreads / 64];
+  const int nk = 2 * kmax + 1;
+  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  fill_twiddles<T, -1>(L.tw, N);
+  const int p = blockIdx.x;
+  const int gl = blockIdx.y;
+  const int i = pairs[p] & 0xffff, j = pairs[p] >> 16;
+  const T* pi = psi + long(i) * ld;
+  const T* pj = psi + long(j) * ld;
+  const cplx<T>* wi = w + (long(gl) * nocc + i) * ld;
+  const cplx<T>* wj = w + (long(gl) * nocc + j) * ld;
+  int gd[OPT];
+  cplx<T> acc[2][OPT];
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    gd[t] = (o < ng) ? gdesc_all[o] : 0;
+    acc[0][t] = {T(0), T(0)};
+    acc[1][t] = {T(0), T(0)};
+  }
+  __syncthreads();
+  auto ld_ = [&](int f, int x, int y, int z) {
+    const long r = (x * N + z) * N + y;
+    const T a = (f == 0) ? pi[r] : pj[r];
+    const cplx<T> b = (f == 0) ? wj[r] : wi[r];
+    return cplx<T>{a * b.x, a * b.y};
+  };
+  forward_pruned<T, -1, N, 2, OPT>(ld_, (i == j) ? 1 : 2, kmax, sx, gd, ng, acc, L);
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    if (o < ng) {
+      const double ar = acc[0][t].x, ai = acc[0][t].y;
+      if (i == j) {
+        s += v[o] * (ar * ar + ai * ai);
+      } else {
+        const double br = acc[1][t].x, bi = acc[1][t].y;
+        s += 2.0 * v[o] * (ar * br + ai * bi);
+      }
+    }
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) xpart[long(gl) * npairs + p] = dV2 * s;
+}
+
+}  // namespace ltmp2

@@ -1,0 +1,742 @@
+// libltmp2: host side of the C ABI (validation, tables, device memory,
+// per-Laplace-point drivers).  The device work is in kernels_*.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ltmp2.h"
+#include "dispatch.h"
+#include "quadrature.h"
+
+using namespace ltmp2;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ltmp2_ctx {
+  ltmp2_params prm{};
+  std::string err;
+  bool failed = false;
+  hipStream_t stream = nullptr;
+
+  // sizes
+  int n = 0, nr = 0, npw = 0, no = 0, nv = 0, ng = 0, nh = 0, ntau = 0, npairs = 0;
+  long nrp = 0;  // padded row stride of grid arrays (multiple of 64)
+  int kmax_aux = 0, kmax_orb = 0, gblock = 0;
+  double omega = 0, dV = 0, mu = 0, xmin = 0, xmax = 0, quad_delta = 0;
+  std::vector<double> eps, tau, w;
+  std::vector<int> aux;  // [ng][3], H first then -H
+
+  // device tables
+  SphereCols sc{};
+  int* d_cdesc = nullptr;
+  int* d_cstart = nullptr;
+  int* d_ckx = nullptr;
+  int* d_wq = nullptr;
+  signed char* d_wsgn = nullptr;
+  int* d_gdesc = nullptr;
+  int* d_pairs = nullptr;
+  double* d_v = nullptr;
+  double* d_fo = nullptr;  // [ntau][no]
+  double* d_fv = nullptr;  // [ntau][nv]
+
+  // device data
+  double* d_psi = nullptr;     // [npw][nrp]
+  double* d_nd = nullptr;      // [nv][nh][no] complex
+  double* d_bpw = nullptr;     // [nv][npw] real basis of virtual coefficients
+  double* d_chi = nullptr;     // [nrp][nrp]
+  double* d_chihat = nullptr;  // [nh][nrp] complex
+  double* d_pd = nullptr;      // [nh]
+  double* d_P = nullptr;       // [gblock * no * 2][npw]
+  double* d_w = nullptr;       // [gblock * no][nrp] complex
+  double* d_xpart = nullptr;   // [nh][npairs]
+  double* d_scal = nullptr;    // [2 * ntau + 8] device scalars
+
+  std::vector<void*> owned;
+  size_t bytes = 0;
+
+  // optional per-stage event timing
+  bool timing = false;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  double stage_ms[8] = {0};
+  long stage_n[8] = {0};
+};
+
+namespace {
+
+ltmp2_status fail(ltmp2_ctx* c, ltmp2_status s, const std::string& msg) {
+  if (c) {
+    c->err = msg;
+    if (s == LTMP2_EDEVICE) c->failed = true;
+  } else {
+    g_setup_error = msg;
+  }
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? LTMP2_ENOMEM : LTMP2_EDEVICE,       \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+bool smooth235(int n) {
+  for (int f : {2, 3, 5})
+    while (n % f == 0) n /= f;
+  return n == 1;
+}
+
+bool positive_half(int a, int b, int c) {
+  if (a != 0) return a > 0;
+  if (b != 0) return b > 0;
+  return c > 0;
+}
+
+template <class T>
+ltmp2_status dalloc(ltmp2_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&q, b);
+  if (e != hipSuccess)
+    return fail(c, e == hipErrorOutOfMemory ? LTMP2_ENOMEM : LTMP2_EDEVICE,
+                "hipMalloc(" + std::to_string(b) + " bytes): " + hipGetErrorString(e));
+  c->owned.push_back(q);
+  c->bytes += b;
+  *p = reinterpret_cast<T*>(q);
+  return LTMP2_OK;
+}
+
+template <class T>
+ltmp2_status upload(ltmp2_ctx* c, T** p, const std::vector<T>& v) {
+  ltmp2_status s = dalloc(c, p, v.size());
+  if (s) return s;
+  if (!v.empty()) HIPCHK(c, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return LTMP2_OK;
+}
+
+// Validation of everything the host receives, before any device call.
+ltmp2_status validate(const ltmp2_params* p, const int32_t* miller, const double* eps,
+                      const double* coeff, const double* tau, const double* w) {
+  if (!p) return fail(nullptr, LTMP2_EINVAL, "params is NULL");
+  if (!(p->L > 0.0) || !std::isfinite(p->L)) return fail(nullptr, LTMP2_EINVAL, "L must be > 0");
+  if (p->n_fft < 4 || p->n_fft > 64 || !smooth235(p->n_fft))
+    return fail(nullptr, LTMP2_EINVAL, "n_fft must be a 2,3,5-smooth size in [4, 64]");
+  if (!grid_supported(p->n_fft))
+    return fail(nullptr, LTMP2_EINVAL, "n_fft " + std::to_string(p->n_fft) + " is not compiled in");
+  if (!(p->ecut > 0.0) || !std::isfinite(p->ecut) || !(p->eaux > 0.0) || !std::isfinite(p->eaux))
+    return fail(nullptr, LTMP2_EINVAL, "ecut and eaux must be > 0");
+  if (p->n_pw < 2) return fail(nullptr, LTMP2_EINVAL, "n_pw must be >= 2");
+  if (p->n_occ < 1 || p->n_occ >= p->n_pw)
+    return fail(nullptr, LTMP2_EINVAL, "n_occ must be in [1, n_pw - 1]");
+  if (p->n_tau < 1 || p->n_tau > 16) return fail(nullptr, LTMP2_EINVAL, "n_tau must be in [1, 16]");
+  if (p->prec < 0 || p->prec > 2) return fail(nullptr, LTMP2_EINVAL, "unknown precision");
+  if (p->quad_mode < 0 || p->quad_mode > 2) return fail(nullptr, LTMP2_EINVAL, "unknown quad_mode");
+  if (p->prec != LTMP2_FP64)
+    return fail(nullptr, LTMP2_EINVAL, "only LTMP2_FP64 is available in this build");
+  if (p->quad_mode == LTMP2_QUAD_LEARNED)
+    return fail(nullptr, LTMP2_EINVAL, "learned quadrature is not available in this build");
+  if (!miller || !eps || !coeff) return fail(nullptr, LTMP2_EINVAL, "NULL input array");
+  if (p->quad_mode == LTMP2_QUAD_GIVEN) {
+    if (!tau || !w) return fail(nullptr, LTMP2_EINVAL, "tau and w required with LTMP2_QUAD_GIVEN");
+    for (int k = 0; k < p->n_tau; ++k)
+      if (!(tau[k] > 0.0) || !(w[k] > 0.0) || !std::isfinite(tau[k]) || !std::isfinite(w[k]))
+        return fail(nullptr, LTMP2_EINVAL, "tau and w must be positive and finite");
+  } else if (tau || w) {
+    return fail(nullptr, LTMP2_EINVAL, "tau / w given but quad_mode is not LTMP2_QUAD_GIVEN");
+  }
+  const int n = p->n_fft, npw = p->n_pw;
+  const double b = 2.0 * M_PI / p->L;
+  std::map<std::tuple<int, int, int>, int> pos;
+  for (int k = 0; k < npw; ++k) {
+    const int a = miller[3 * k], bb = miller[3 * k + 1], c = miller[3 * k + 2];
+    if (2 * std::abs(a) >= n || 2 * std::abs(bb) >= n || 2 * std::abs(c) >= n)
+      return fail(nullptr, LTMP2_EINVAL, "basis vector outside the centred FFT grid");
+    const double g2 = b * b * double(a * a + bb * bb + c * c);
+    if (!(0.5 * g2 < p->ecut)) return fail(nullptr, LTMP2_EINVAL, "basis vector beyond ecut");
+    if (!pos.emplace(std::make_tuple(a, bb, c), k).second)
+      return fail(nullptr, LTMP2_EINVAL, "duplicate Miller index");
+  }
+  for (int k = 0; k < npw; ++k)
+    if (!pos.count(std::make_tuple(-miller[3 * k], -miller[3 * k + 1], -miller[3 * k + 2])))
+      return fail(nullptr, LTMP2_EINVAL, "basis not closed under G -> -G");
+  for (int k = 0; k < npw; ++k) {
+    if (!std::isfinite(eps[k])) return fail(nullptr, LTMP2_EINVAL, "non-finite orbital energy");
+    if (k > 0 && eps[k] < eps[k - 1]) return fail(nullptr, LTMP2_EINVAL, "eps must be ascending");
+  }
+  if (!(eps[p->n_occ] - eps[p->n_occ - 1] > 1e-8))
+    return fail(nullptr, LTMP2_EGAP, "HOMO-LUMO gap <= 1e-8 Ha");
+  std::vector<int> negi(npw);
+  for (int k = 0; k < npw; ++k)
+    negi[k] = pos[std::make_tuple(-miller[3 * k], -miller[3 * k + 1], -miller[3 * k + 2])];
+  for (int s = 0; s < npw; ++s) {
+    const double* c = coeff + 2 * size_t(s) * npw;
+    double nrm = 0.0, asym = 0.0;
+    for (int k = 0; k < npw; ++k) {
+      if (!std::isfinite(c[2 * k]) || !std::isfinite(c[2 * k + 1]))
+        return fail(nullptr, LTMP2_EINVAL, "non-finite coefficient");
+      nrm += c[2 * k] * c[2 * k] + c[2 * k + 1] * c[2 * k + 1];
+      const int m = negi[k];
+      asym = std::max(asym, std::fabs(c[2 * m] - c[2 * k]) + std::fabs(c[2 * m + 1] + c[2 * k + 1]));
+    }
+    if (std::fabs(nrm - 1.0) > 1e-8) return fail(nullptr, LTMP2_EINVAL, "state not normalised");
+    if (asym > 1e-10)
+      return fail(nullptr, LTMP2_EINVAL,
+                  "orbital " + std::to_string(s) + " is not real on the grid (c(-G) != conj c(G))");
+  }
+  return LTMP2_OK;
+}
+
+// Launch helpers --------------------------------------------------------------
+ltmp2_status check_launch(ltmp2_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(c, LTMP2_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return LTMP2_OK;
+}
+
+hipEvent_t pooled_event(ltmp2_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when timing is on.
+struct StageTimer {
+  ltmp2_ctx* c;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageTimer(ltmp2_ctx* cc, int s) : c(cc), stage(s) {
+    if (c->timing && (a = pooled_event(c))) (void)hipEventRecord(a, c->stream);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = pooled_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->marks.push_back({stage, a, b});
+  }
+};
+
+void collect_timing(ltmp2_ctx* c) {
+  if (c->marks.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& m : c->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+      c->stage_ms[m.stage] += ms;
+      c->stage_n[m.stage] += 1;
+    }
+    c->pool.push_back(m.a);
+    c->pool.push_back(m.b);
+  }
+  c->marks.clear();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" ltmp2_status ltmp2_quadrature(double x_min, double x_max, int n_tau, double* tau,
+                                         double* w, double* delta) {
+  if (!tau || !w) return fail(nullptr, LTMP2_EINVAL, "NULL output");
+  const int r = minimax_quadrature(x_min, x_max, n_tau, tau, w, delta);
+  if (r == 1) return fail(nullptr, LTMP2_EINVAL, "need 0 < x_min < x_max and 1 <= n_tau <= 16");
+  if (r != 0) return fail(nullptr, LTMP2_ENUMERIC, "minimax fit did not converge");
+  return LTMP2_OK;
+}
+
+extern "C" int ltmp2_supported_grids(int* sizes, int cap) {
+  std::vector<int> g = supported_grids();
+  for (int k = 0; k < (int)g.size() && k < cap; ++k) sizes[k] = g[k];
+  return (int)g.size();
+}
+
+namespace {
+
+ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
+                        const double* coeff, const double* tau, const double* w) {
+  const ltmp2_params& P = c->prm;
+  const int n = P.n_fft;
+  c->n = n;
+  c->nr = n * n * n;
+  c->nrp = (c->nr + 63) / 64 * 64;
+  c->npw = P.n_pw;
+  c->no = P.n_occ;
+  c->nv = P.n_pw - P.n_occ;
+  c->ntau = P.n_tau;
+  c->omega = P.L * P.L * P.L;
+  c->dV = c->omega / c->nr;
+  c->eps.assign(eps, eps + P.n_pw);
+  c->mu = 0.5 * (eps[c->no - 1] + eps[c->no]);
+  c->xmin = 2.0 * (eps[c->no] - eps[c->no - 1]);
+  c->xmax = 2.0 * (eps[P.n_pw - 1] - eps[0]);
+  c->npairs = c->no * (c->no + 1) / 2;
+  if (c->npairs > (1 << 22) || c->no >= (1 << 15))
+    return fail(nullptr, LTMP2_EINVAL, "too many occupied states");
+
+  // auxiliary set: H (positive half, lexicographic), then -H
+  const double b = 2.0 * M_PI / P.L;
+  const int lim = int(std::floor(2.0 * P.eaux / (b * b) + 1e-9));
+  const int mm = int(std::sqrt(double(lim))) + 1;
+  std::vector<std::array<int, 3>> H;
+  for (int x = -mm; x <= mm; ++x)
+    for (int y = -mm; y <= mm; ++y)
+      for (int z = -mm; z <= mm; ++z) {
+        const int m2 = x * x + y * y + z * z;
+        if (m2 == 0 || m2 > lim || !positive_half(x, y, z)) continue;
+        if (2 * std::abs(x) >= n || 2 * std::abs(y) >= n || 2 * std::abs(z) >= n)
+          return fail(nullptr, LTMP2_EINVAL, "auxiliary sphere does not fit inside the FFT grid");
+        H.push_back({x, y, z});
+      }
+  if (H.empty()) return fail(nullptr, LTMP2_EINVAL, "auxiliary set is empty");
+  c->nh = (int)H.size();
+  c->ng = 2 * c->nh;
+  if (c->ng > max_outputs()) return fail(nullptr, LTMP2_EINVAL, "auxiliary set too large");
+  c->aux.resize(3 * c->ng);
+  int km = 0;
+  for (int k = 0; k < c->nh; ++k)
+    for (int d = 0; d < 3; ++d) {
+      c->aux[3 * k + d] = H[k][d];
+      c->aux[3 * (k + c->nh) + d] = -H[k][d];
+      km = std::max(km, std::abs(H[k][d]));
+    }
+  c->kmax_aux = km;
+  std::vector<int> gdesc(c->ng);
+  std::vector<double> v(c->ng);
+  for (int k = 0; k < c->ng; ++k) {
+    const int x = c->aux[3 * k], y = c->aux[3 * k + 1], z = c->aux[3 * k + 2];
+    gdesc[k] = pack_g(((x % n) + n) % n, y + km, z + km);
+    v[k] = 4.0 * M_PI / (c->omega * b * b * double(x * x + y * y + z * z));
+  }
+
+  // orbital sphere in (ky, kz) column order
+  int ko = 0;
+  for (int k = 0; k < c->npw; ++k)
+    for (int d = 0; d < 3; ++d) ko = std::max(ko, std::abs(miller[3 * k + d]));
+  c->kmax_orb = ko;
+  std::vector<int> order(c->npw);
+  for (int k = 0; k < c->npw; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), [&](int a, int bq) {
+    auto key = [&](int i) {
+      return std::make_tuple(miller[3 * i + 1], miller[3 * i + 2], miller[3 * i]);
+    };
+    return key(a) < key(bq);
+  });
+  std::vector<int> cdesc, cstart, ckx(c->npw);
+  for (int e = 0; e < c->npw; ++e) {
+    const int i = order[e];
+    const int ky = miller[3 * i + 1], kz = miller[3 * i + 2];
+    if (e == 0 || ky != miller[3 * order[e - 1] + 1] || kz != miller[3 * order[e - 1] + 2]) {
+      cdesc.push_back((ky + ko) | ((kz + ko) << 8));
+      cstart.push_back(e);
+    }
+    ckx[e] = miller[3 * i];
+  }
+  cstart.push_back(c->npw);
+  // real basis of the coefficients: q = 0 for G = 0, (2k+1, 2k+2) for the
+  // k-th basis vector of the positive half (in input order)
+  std::map<std::tuple<int, int, int>, int> qre;
+  int nq = 1, zero_idx = -1;
+  for (int k = 0; k < c->npw; ++k) {
+    const int x = miller[3 * k], y = miller[3 * k + 1], z = miller[3 * k + 2];
+    if (x == 0 && y == 0 && z == 0) zero_idx = k;
+    if (positive_half(x, y, z)) {
+      qre[std::make_tuple(x, y, z)] = nq;
+      nq += 2;
+    }
+  }
+  if (zero_idx < 0 || nq != c->npw)
+    return fail(nullptr, LTMP2_EINVAL, "basis must contain G = 0 and be symmetric");
+  std::vector<int> wq(c->npw);
+  std::vector<signed char> wsgn(c->npw);
+  for (int e = 0; e < c->npw; ++e) {
+    const int i = order[e];
+    const int x = miller[3 * i], y = miller[3 * i + 1], z = miller[3 * i + 2];
+    if (x == 0 && y == 0 && z == 0) {
+      wq[e] = 0;
+      wsgn[e] = 1;
+    } else if (positive_half(x, y, z)) {
+      const int q = qre[std::make_tuple(x, y, z)];
+      wq[e] = q | ((q + 1 + 1) << 16);
+      wsgn[e] = 1;
+    } else {
+      const int q = qre[std::make_tuple(-x, -y, -z)];
+      wq[e] = q | ((q + 1 + 1) << 16);
+      wsgn[e] = -1;
+    }
+  }
+  // coefficients in column order, and the real basis of the virtual ones
+  std::vector<double> coef_col(2 * size_t(c->npw) * c->npw);
+  std::vector<double> bpw(size_t(c->nv) * c->npw);
+  for (int s = 0; s < c->npw; ++s) {
+    const double* cs = coeff + 2 * size_t(s) * c->npw;
+    for (int e = 0; e < c->npw; ++e) {
+      coef_col[2 * (size_t(s) * c->npw + e)] = cs[2 * order[e]];
+      coef_col[2 * (size_t(s) * c->npw + e) + 1] = cs[2 * order[e] + 1];
+    }
+    if (s >= c->no) {
+      double* row = bpw.data() + size_t(s - c->no) * c->npw;
+      row[0] = cs[2 * zero_idx];
+      for (int k = 0; k < c->npw; ++k) {
+        const int x = miller[3 * k], y = miller[3 * k + 1], z = miller[3 * k + 2];
+        if (!positive_half(x, y, z)) continue;
+        const int q = qre[std::make_tuple(x, y, z)];
+        row[q] = cs[2 * k];
+        row[q + 1] = cs[2 * k + 1];
+      }
+    }
+  }
+  std::vector<int> pairs;
+  for (int i = 0; i < c->no; ++i)
+    for (int j = i; j < c->no; ++j) pairs.push_back(i | (j << 16));
+
+  // quadrature
+  c->tau.resize(c->ntau);
+  c->w.resize(c->ntau);
+  if (P.quad_mode == LTMP2_QUAD_GIVEN) {
+    c->tau.assign(tau, tau + c->ntau);
+    c->w.assign(w, w + c->ntau);
+    double d = 0.0;
+    const int ng = 20000;
+    for (int k = 0; k < ng; ++k) {
+      const double x = c->xmin * std::exp(std::log(c->xmax / c->xmin) * k / (ng - 1));
+      double s = 0.0;
+      for (int t = 0; t < c->ntau; ++t) s += c->w[t] * std::exp(-x * c->tau[t]);
+      d = std::max(d, std::fabs(x * s - 1.0));
+    }
+    c->quad_delta = d;
+  } else {
+    const int r = minimax_quadrature(c->xmin, c->xmax, c->ntau, c->tau.data(), c->w.data(),
+                                     &c->quad_delta);
+    if (r != 0) return fail(nullptr, LTMP2_ENUMERIC, "minimax quadrature did not converge");
+  }
+  std::vector<double> fo(size_t(c->ntau) * c->no), fv(size_t(c->ntau) * c->nv);
+  for (int t = 0; t < c->ntau; ++t) {
+    for (int i = 0; i < c->no; ++i) fo[size_t(t) * c->no + i] = std::exp((eps[i] - c->mu) * c->tau[t]);
+    for (int a = 0; a < c->nv; ++a)
+      fv[size_t(t) * c->nv + a] = std::exp(-(eps[c->no + a] - c->mu) * c->tau[t]);
+  }
+
+  // device footprint and G'-block size
+  const size_t nrp = c->nrp;
+  size_t fixed = sizeof(double) * (size_t(c->npw) * nrp + 2 * size_t(c->nv) * c->nh * c->no +
+                                   size_t(c->nv) * c->npw + nrp * nrp + 2 * size_t(c->nh) * nrp +
+                                   size_t(c->nh) + size_t(c->nh) * c->npairs) +
+                 sizeof(double) * 2 * size_t(c->npw) * c->npw;
+  const size_t per_g = sizeof(double) * (2 * size_t(c->no) * c->npw + 2 * size_t(c->no) * nrp);
+  size_t budget = size_t(8) << 30;
+  if (P.workspace_cap) {
+    if (fixed + per_g > P.workspace_cap)
+      return fail(nullptr, LTMP2_ENOMEM, "workspace cap below the minimum device footprint");
+    budget = std::min(budget, P.workspace_cap - fixed);
+  }
+  c->gblock = (int)std::max<size_t>(1, std::min<size_t>(c->nh, budget / per_g));
+
+  // device allocations and uploads
+  ltmp2_status s;
+  if ((s = upload(c, &c->d_cdesc, cdesc)) || (s = upload(c, &c->d_cstart, cstart)) ||
+      (s = upload(c, &c->d_ckx, ckx)) || (s = upload(c, &c->d_wq, wq)) ||
+      (s = upload(c, &c->d_wsgn, wsgn)) || (s = upload(c, &c->d_gdesc, gdesc)) ||
+      (s = upload(c, &c->d_pairs, pairs)) || (s = upload(c, &c->d_v, v)) ||
+      (s = upload(c, &c->d_fo, fo)) || (s = upload(c, &c->d_fv, fv)) ||
+      (s = upload(c, &c->d_bpw, bpw)))
+    return s;
+  c->sc = SphereCols{(int)cdesc.size(), ko, c->d_cdesc, c->d_cstart, c->d_ckx};
+  double* d_coef = nullptr;
+  if ((s = upload(c, &d_coef, coef_col))) return s;
+  if ((s = dalloc(c, &c->d_psi, size_t(c->npw) * nrp)) ||
+      (s = dalloc(c, &c->d_nd, 2 * size_t(c->nv) * c->nh * c->no)) ||
+      (s = dalloc(c, &c->d_chi, nrp * nrp)) || (s = dalloc(c, &c->d_chihat, 2 * size_t(c->nh) * nrp)) ||
+      (s = dalloc(c, &c->d_pd, c->nh)) ||
+      (s = dalloc(c, &c->d_P, 2 * size_t(c->gblock) * c->no * c->npw)) ||
+      (s = dalloc(c, &c->d_w, 2 * size_t(c->gblock) * c->no * nrp)) ||
+      (s = dalloc(c, &c->d_xpart, size_t(c->nh) * c->npairs)) ||
+      (s = dalloc(c, &c->d_scal, 2 * size_t(c->ntau) + 8)))
+    return s;
+  if (P.workspace_cap && c->bytes > P.workspace_cap)
+    return fail(nullptr, LTMP2_ENOMEM, "device footprint exceeds the workspace cap");
+  HIPCHK(c, hipMemsetAsync(c->d_psi, 0, sizeof(double) * size_t(c->npw) * nrp, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_scal, 0, sizeof(double) * (2 * size_t(c->ntau) + 8), c->stream));
+
+  // orbitals on the grid, then overlap densities (step (i))
+  if ((s = launch_orbitals(c->n, reinterpret_cast<const cplx<double>*>(d_coef), c->npw, c->sc,
+                           1.0 / std::sqrt(c->omega), c->d_psi, c->nrp, c->stream)))
+    return fail(nullptr, s, "orbital synthesis launch failed");
+  if ((s = launch_overlap(c->n, c->d_psi, c->nrp, c->no, c->nv, c->d_gdesc, c->nh, c->kmax_aux,
+                          c->dV, reinterpret_cast<cplx<double>*>(c->d_nd), c->stream)))
+    return fail(nullptr, s, "overlap-density launch failed");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LTMP2_OK;
+}
+
+ltmp2_status usable(ltmp2_ctx* c, int itau) {
+  if (!c) return LTMP2_EINVAL;
+  if (c->failed) return fail(c, LTMP2_ESTATE, "context failed earlier: " + c->err);
+  if (itau < 0 || itau >= c->ntau) return fail(c, LTMP2_EINVAL, "itau out of range");
+  return LTMP2_OK;
+}
+
+// direct term at one Laplace point; value left in d_scal[2 * itau]
+ltmp2_status run_direct(ltmp2_ctx* c, int itau, double* chi_out) {
+  ltmp2_status s;
+  const double* fo = c->d_fo + size_t(itau) * c->no;
+  const double* fv = c->d_fv + size_t(itau) * c->nv;
+  const int nt = int(c->nrp / 64);
+  {
+  StageTimer tm(c, 0);
+  hipLaunchKernelGGL(k_gf_chi, dim3(unsigned(long(nt) * (nt + 1) / 2)), dim3(256), 0, c->stream,
+                     c->d_psi, c->nrp, c->no, c->nv, fo, fv, c->d_chi, c->nrp);
+  }
+  if ((s = check_launch(c, "k_gf_chi"))) return s;
+  {
+  StageTimer tm(c, 1);
+  s = launch_chi_rows(c->n, c->d_chi, c->nrp, c->nr, c->d_gdesc, c->nh, c->kmax_aux, c->dV,
+                           reinterpret_cast<cplx<double>*>(c->d_chihat), c->stream);
+  }
+  if (s) return fail(c, s, "chi row transform launch failed");
+  {
+  StageTimer tm(c, 2);
+  s = launch_chi_cols(c->n, reinterpret_cast<const cplx<double>*>(c->d_chihat), c->nrp,
+                           c->d_gdesc, c->ng, c->nh, c->d_v, c->kmax_aux, c->dV, c->d_pd,
+                           reinterpret_cast<cplx<double>*>(chi_out), c->stream);
+  }
+  if (s) return fail(c, s, "chi column transform launch failed");
+  StageTimer tm(c, 6);
+  hipLaunchKernelGGL(k_reduce_direct, dim3(1), dim3(256), 0, c->stream, c->d_pd, c->nh,
+                     c->d_scal + 2 * itau);
+  return check_launch(c, "k_reduce_direct");
+}
+
+// exchange term at one Laplace point for G' in H[g_first, g_first + g_count)
+ltmp2_status run_exchange(ltmp2_ctx* c, int itau, int g_first, int g_count) {
+  ltmp2_status s;
+  const double* fo = c->d_fo + size_t(itau) * c->no;
+  const double* fv = c->d_fv + size_t(itau) * c->nv;
+  const long lda = 2L * c->nh * c->no;
+  for (int g0 = g_first; g0 < g_first + g_count; g0 += c->gblock) {
+    const int gb = std::min(c->gblock, g_first + g_count - g0);
+    const int M = 2 * gb * c->no;
+    // P = C Psi_v in the real basis:  C_ja = fo_j fv_a n_aj(G')
+    {
+    StageTimer tm(c, 3);
+    hipLaunchKernelGGL(k_gemm_kmajor, dim3((c->npw + 63) / 64, (M + 63) / 64), dim3(256), 0,
+                       c->stream, c->d_nd + 2L * g0 * c->no, lda, c->d_bpw, (long)c->npw, c->d_P,
+                       (long)c->npw, M, c->npw, c->nv, fv, fo, 2, c->no);
+    }
+    if ((s = check_launch(c, "k_gemm_kmajor(W)"))) return s;
+    {
+    StageTimer tm(c, 4);
+    s = launch_wstates(c->n, c->d_P, c->npw, c->d_wq, c->d_wsgn, c->sc, gb * c->no,
+                            1.0 / std::sqrt(c->omega), reinterpret_cast<cplx<double>*>(c->d_w),
+                            c->nrp, c->stream);
+    }
+    if (s) return fail(c, s, "transformed-state launch failed");
+    {
+    StageTimer tm(c, 5);
+    s = launch_pair(c->n, c->d_psi, c->nrp, reinterpret_cast<const cplx<double>*>(c->d_w),
+                         c->no, c->d_pairs, c->npairs, gb, c->d_gdesc, c->ng, c->d_v, c->kmax_aux,
+                         c->dV * c->dV, c->d_xpart + size_t(g0) * c->npairs, c->stream);
+    }
+    if (s) return fail(c, s, "pair transform launch failed");
+  }
+  StageTimer tm(c, 6);
+  hipLaunchKernelGGL(k_reduce_exchange, dim3(1), dim3(256), 0, c->stream, c->d_xpart, g_first,
+                     g_count, c->npairs, c->d_v, c->d_scal + 2 * itau + 1);
+  return check_launch(c, "k_reduce_exchange");
+}
+
+}  // namespace
+
+extern "C" ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller,
+                                    const double* eps, const double* coeff, const double* tau,
+                                    const double* w, const char* mlp_weights, void* hip_stream,
+                                    ltmp2_ctx** out) {
+  (void)mlp_weights;
+  if (!out) return fail(nullptr, LTMP2_EINVAL, "out is NULL");
+  *out = nullptr;
+  ltmp2_status s = validate(p, miller, eps, coeff, tau, w);
+  if (s) return s;
+  ltmp2_ctx* c = new ltmp2_ctx();
+  c->prm = *p;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  s = setup_impl(c, miller, eps, coeff, tau, w);
+  if (s) {
+    if (!c->err.empty() && g_setup_error.empty()) g_setup_error = c->err;
+    ltmp2_destroy(c);
+    return s;
+  }
+  *out = c;
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_green(ltmp2_ctx* c, int itau, int row0, int nrows, void* gocc,
+                                    void* gvir) {
+  ltmp2_status s = usable(c, itau);
+  if (s) return s;
+  if (row0 < 0 || nrows < 0 || row0 + nrows > c->nr)
+    return fail(c, LTMP2_EINVAL, "row range outside [0, n_r)");
+  if (nrows == 0) return LTMP2_OK;
+  const double* fo = c->d_fo + size_t(itau) * c->no;
+  const double* fv = c->d_fv + size_t(itau) * c->nv;
+  if (gocc) {
+    hipLaunchKernelGGL(k_gemm_kmajor, dim3((c->nr + 63) / 64, (nrows + 63) / 64), dim3(256), 0,
+                       c->stream, c->d_psi + row0, c->nrp, c->d_psi, c->nrp,
+                       reinterpret_cast<double*>(gocc), (long)c->nr, nrows, c->nr, c->no, fo,
+                       (const double*)nullptr, 1, 1);
+    if ((s = check_launch(c, "k_gemm_kmajor(G_occ)"))) return s;
+  }
+  if (gvir) {
+    const double* pv = c->d_psi + size_t(c->no) * c->nrp;
+    hipLaunchKernelGGL(k_gemm_kmajor, dim3((c->nr + 63) / 64, (nrows + 63) / 64), dim3(256), 0,
+                       c->stream, pv + row0, c->nrp, pv, c->nrp, reinterpret_cast<double*>(gvir),
+                       (long)c->nr, nrows, c->nr, c->nv, fv, (const double*)nullptr, 1, 1);
+    if ((s = check_launch(c, "k_gemm_kmajor(G_vir)"))) return s;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_chi(ltmp2_ctx* c, int itau, void* chi_GG_dev, double* e_direct_tau) {
+  ltmp2_status s = usable(c, itau);
+  if (s) return s;
+  if ((s = run_direct(c, itau, reinterpret_cast<double*>(chi_GG_dev)))) return s;
+  double v = 0.0;
+  HIPCHK(c, hipMemcpyAsync(&v, c->d_scal + 2 * itau, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!std::isfinite(v)) return fail(c, LTMP2_ENUMERIC, "non-finite direct term");
+  if (e_direct_tau) *e_direct_tau = v;
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_exchange(ltmp2_ctx* c, int itau, int g_first, int g_count,
+                                       double* e_exchange_tau) {
+  ltmp2_status s = usable(c, itau);
+  if (s) return s;
+  if (g_count <= 0) {
+    g_first = 0;
+    g_count = c->nh;
+  }
+  if (g_first < 0 || g_first + g_count > c->nh) return fail(c, LTMP2_EINVAL, "G' range outside H");
+  if ((s = run_exchange(c, itau, g_first, g_count))) return s;
+  double v = 0.0;
+  HIPCHK(c, hipMemcpyAsync(&v, c->d_scal + 2 * itau + 1, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!std::isfinite(v)) return fail(c, LTMP2_ENUMERIC, "non-finite exchange term");
+  if (e_exchange_tau) *e_exchange_tau = v;
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_energy(ltmp2_ctx* c, double* e_direct, double* e_exchange,
+                                     double* per_tau, double* quad_err) {
+  ltmp2_status s = usable(c, 0);
+  if (s) return s;
+  for (int t = 0; t < c->ntau; ++t) {
+    if ((s = run_direct(c, t, nullptr))) return s;
+    if ((s = run_exchange(c, t, 0, c->nh))) return s;
+  }
+  std::vector<double> pt(2 * size_t(c->ntau));
+  HIPCHK(c, hipMemcpyAsync(pt.data(), c->d_scal, sizeof(double) * pt.size(), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double ed = 0.0, ex = 0.0;
+  for (int t = 0; t < c->ntau; ++t) {
+    ed += c->w[t] * pt[2 * t];
+    ex += c->w[t] * pt[2 * t + 1];
+  }
+  if (!std::isfinite(ed) || !std::isfinite(ex)) return fail(c, LTMP2_ENUMERIC, "non-finite energy");
+  if (e_direct) *e_direct = ed;
+  if (e_exchange) *e_exchange = ex;
+  if (per_tau) std::copy(pt.begin(), pt.end(), per_tau);
+  if (quad_err) *quad_err = c->quad_delta;
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_get_quadrature(const ltmp2_ctx* c, double* tau, double* w,
+                                             double* delta) {
+  if (!c) return LTMP2_EINVAL;
+  if (tau) std::copy(c->tau.begin(), c->tau.end(), tau);
+  if (w) std::copy(c->w.begin(), c->w.end(), w);
+  if (delta) *delta = c->quad_delta;
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_get_info(const ltmp2_ctx* c, ltmp2_info* info) {
+  if (!c || !info) return LTMP2_EINVAL;
+  info->n_r = c->nr;
+  info->n_g = c->ng;
+  info->n_h = c->nh;
+  info->n_pw = c->npw;
+  info->n_occ = c->no;
+  info->n_vir = c->nv;
+  info->n_tau = c->ntau;
+  info->x_min = c->xmin;
+  info->x_max = c->xmax;
+  info->quad_delta = c->quad_delta;
+  info->device_bytes = c->bytes;
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_aux_miller(const ltmp2_ctx* c, int32_t* out) {
+  if (!c || !out) return LTMP2_EINVAL;
+  std::copy(c->aux.begin(), c->aux.end(), out);
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_set_timing(ltmp2_ctx* c, int on) {
+  if (!c) return LTMP2_EINVAL;
+  collect_timing(c);
+  c->timing = on != 0;
+  for (int k = 0; k < 8; ++k) {
+    c->stage_ms[k] = 0.0;
+    c->stage_n[k] = 0;
+  }
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_get_timing(ltmp2_ctx* c, int stage, double* ms, long* launches) {
+  if (!c || stage < 0 || stage > 6) return LTMP2_EINVAL;
+  collect_timing(c);
+  if (ms) *ms = c->stage_ms[stage];
+  if (launches) *launches = c->stage_n[stage];
+  return LTMP2_OK;
+}
+
+extern "C" void ltmp2_destroy(ltmp2_ctx* c) {
+  if (!c) return;
+  if (c->stream || !c->owned.empty()) (void)hipStreamSynchronize(c->stream);
+  collect_timing(c);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  for (void* p : c->owned) (void)hipFree(p);
+  delete c;
+}
+
+extern "C" const char* ltmp2_last_error(const ltmp2_ctx* c) {
+  return c ? c->err.c_str() : g_setup_error.c_str();
+}

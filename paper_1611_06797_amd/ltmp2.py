@@ -1,0 +1,245 @@
+"""Thin ctypes binding of libltmp2 (argument marshalling only).
+
+Every step of the LTMP2 path runs inside the HIP library; this module only
+converts numpy arrays / torch device tensors into pointers and status codes
+into exceptions.  PyTorch is used for device buffers and the current HIP
+stream.  Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libltmp2.so")
+
+STATUS = {0: "LTMP2_OK", 1: "LTMP2_EINVAL", 2: "LTMP2_EGAP", 3: "LTMP2_ENOMEM",
+          4: "LTMP2_EDEVICE", 5: "LTMP2_ESTATE", 6: "LTMP2_ENUMERIC"}
+FP64, FP32, BF16X3 = 0, 1, 2
+QUAD_PLAIN, QUAD_LEARNED, QUAD_GIVEN = 0, 1, 2
+
+EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
+            "ltmp2_get_quadrature", "ltmp2_get_info", "ltmp2_aux_miller", "ltmp2_quadrature",
+            "ltmp2_destroy", "ltmp2_last_error", "ltmp2_supported_grids", "ltmp2_set_timing",
+            "ltmp2_get_timing")
+STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
+
+
+class Params(C.Structure):
+    _fields_ = [("L", C.c_double), ("n_fft", C.c_int), ("ecut", C.c_double),
+                ("eaux", C.c_double), ("n_pw", C.c_int), ("n_occ", C.c_int),
+                ("n_tau", C.c_int), ("quad_mode", C.c_int), ("prec", C.c_int),
+                ("workspace_cap", C.c_size_t)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_r", C.c_int), ("n_g", C.c_int), ("n_h", C.c_int), ("n_pw", C.c_int),
+                ("n_occ", C.c_int), ("n_vir", C.c_int), ("n_tau", C.c_int),
+                ("x_min", C.c_double), ("x_max", C.c_double), ("quad_delta", C.c_double),
+                ("device_bytes", C.c_size_t)]
+
+
+class LTMP2Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libltmp2.so (import torch first so one HIP runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401  (shares its HIP runtime with the library)
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    lib.ltmp2_setup.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_char_p, C.c_void_p,
+                                C.POINTER(C.c_void_p)]
+    lib.ltmp2_green.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    lib.ltmp2_chi.argtypes = [C.c_void_p, C.c_int, C.c_void_p, dp]
+    lib.ltmp2_exchange.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, dp]
+    lib.ltmp2_energy.argtypes = [C.c_void_p, dp, dp, C.c_void_p, dp]
+    lib.ltmp2_get_quadrature.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp]
+    lib.ltmp2_get_info.argtypes = [C.c_void_p, C.POINTER(Info)]
+    lib.ltmp2_aux_miller.argtypes = [C.c_void_p, C.c_void_p]
+    lib.ltmp2_quadrature.argtypes = [C.c_double, C.c_double, C.c_int, C.c_void_p, C.c_void_p, dp]
+    lib.ltmp2_destroy.argtypes = [C.c_void_p]
+    lib.ltmp2_destroy.restype = None
+    lib.ltmp2_last_error.argtypes = [C.c_void_p]
+    lib.ltmp2_last_error.restype = C.c_char_p
+    lib.ltmp2_supported_grids.argtypes = [C.c_void_p, C.c_int]
+    lib.ltmp2_set_timing.argtypes = [C.c_void_p, C.c_int]
+    lib.ltmp2_get_timing.argtypes = [C.c_void_p, C.c_int, dp, C.POINTER(C.c_long)]
+    for name in ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
+                 "ltmp2_get_quadrature", "ltmp2_get_info", "ltmp2_aux_miller",
+                 "ltmp2_quadrature", "ltmp2_set_timing", "ltmp2_get_timing"):
+        getattr(lib, name).restype = C.c_int
+    lib.ltmp2_supported_grids.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _check(lib, st, ctx=None):
+    if st != 0:
+        raise LTMP2Error(st, lib.ltmp2_last_error(ctx).decode())
+
+
+def supported_grids():
+    lib = load()
+    buf = np.zeros(64, np.int32)
+    k = lib.ltmp2_supported_grids(_ptr(buf), 64)
+    return [int(x) for x in buf[:k]]
+
+
+def quadrature(x_min: float, x_max: float, n_tau: int):
+    """Host minimax Laplace quadrature (tau, w, delta) from the library."""
+    lib = load()
+    tau = np.zeros(n_tau)
+    w = np.zeros(n_tau)
+    d = C.c_double()
+    _check(lib, lib.ltmp2_quadrature(x_min, x_max, n_tau, _ptr(tau), _ptr(w), C.byref(d)))
+    return tau, w, d.value
+
+
+class Context:
+    """One prepared cell (ltmp2_setup ... ltmp2_destroy)."""
+
+    def __init__(self, L, n_fft, ecut, eaux, miller, eps, coeff, n_occ, n_tau,
+                 tau=None, w=None, prec=FP64, workspace_cap=0, stream=None,
+                 quad_mode=None, mlp_weights=None):
+        self.lib = load()
+        miller = np.ascontiguousarray(miller, np.int32)
+        eps = np.ascontiguousarray(eps, np.float64)
+        coeff = np.asarray(coeff)
+        if np.iscomplexobj(coeff):
+            coeff = np.stack([coeff.real, coeff.imag], axis=-1)
+        coeff = np.ascontiguousarray(coeff, np.float64)
+        if quad_mode is None:
+            quad_mode = QUAD_GIVEN if tau is not None else QUAD_PLAIN
+        tau_a = None if tau is None else np.ascontiguousarray(tau, np.float64)
+        w_a = None if w is None else np.ascontiguousarray(w, np.float64)
+        p = Params(float(L), int(n_fft), float(ecut), float(eaux), int(miller.shape[0]),
+                   int(n_occ), int(n_tau), int(quad_mode), int(prec), int(workspace_cap))
+        if stream is None:
+            stream = _current_stream()
+        self._ctx = C.c_void_p()
+        st = self.lib.ltmp2_setup(C.byref(p), _ptr(miller), _ptr(eps), _ptr(coeff), _ptr(tau_a),
+                                  _ptr(w_a), mlp_weights.encode() if mlp_weights else None,
+                                  C.c_void_p(stream), C.byref(self._ctx))
+        _check(self.lib, st)
+        self.info = self.get_info()
+
+    # -- lifetime --
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            self.lib.ltmp2_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- queries --
+    def get_info(self):
+        info = Info()
+        _check(self.lib, self.lib.ltmp2_get_info(self._ctx, C.byref(info)), self._ctx)
+        return info
+
+    def get_quadrature(self):
+        n = self.info.n_tau
+        tau = np.zeros(n)
+        w = np.zeros(n)
+        d = C.c_double()
+        _check(self.lib, self.lib.ltmp2_get_quadrature(self._ctx, _ptr(tau), _ptr(w), C.byref(d)),
+               self._ctx)
+        return tau, w, d.value
+
+    def aux_miller(self):
+        out = np.zeros((self.info.n_g, 3), np.int32)
+        _check(self.lib, self.lib.ltmp2_aux_miller(self._ctx, _ptr(out)), self._ctx)
+        return out
+
+    def set_timing(self, on=True):
+        _check(self.lib, self.lib.ltmp2_set_timing(self._ctx, int(on)), self._ctx)
+
+    def get_timing(self):
+        """{stage: (ms, launches)} accumulated since set_timing(True)."""
+        out = {}
+        for k, name in enumerate(STAGES):
+            ms = C.c_double()
+            n = C.c_long()
+            _check(self.lib, self.lib.ltmp2_get_timing(self._ctx, k, C.byref(ms), C.byref(n)),
+                   self._ctx)
+            out[name] = (ms.value, n.value)
+        return out
+
+    # -- the hot path --
+    def green(self, itau, row0, nrows, gocc=None, gvir=None):
+        """Rows of G_occ / G_vir into torch float64 device tensors [nrows, n_r]."""
+        st = self.lib.ltmp2_green(self._ctx, itau, row0, nrows, _dptr(gocc), _dptr(gvir))
+        _check(self.lib, st, self._ctx)
+
+    def chi(self, itau, chi_out=None):
+        """Unweighted E_d(tau); optional chi(G, G') into a complex128 tensor [n_g, n_g]."""
+        e = C.c_double()
+        st = self.lib.ltmp2_chi(self._ctx, itau, _dptr(chi_out), C.byref(e))
+        _check(self.lib, st, self._ctx)
+        return e.value
+
+    def exchange(self, itau, g_first=0, g_count=0):
+        """Unweighted E_x(tau) over the outer G' range of the half set (0: all)."""
+        e = C.c_double()
+        st = self.lib.ltmp2_exchange(self._ctx, itau, g_first, g_count, C.byref(e))
+        _check(self.lib, st, self._ctx)
+        return e.value
+
+    def energy(self):
+        """(E_d, E_x, per_tau [n_tau, 2], quad_err)."""
+        ed = C.c_double()
+        ex = C.c_double()
+        qe = C.c_double()
+        pt = np.zeros(2 * self.info.n_tau)
+        st = self.lib.ltmp2_energy(self._ctx, C.byref(ed), C.byref(ex), _ptr(pt), C.byref(qe))
+        _check(self.lib, st, self._ctx)
+        return ed.value, ex.value, pt.reshape(-1, 2), qe.value
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device output must be a contiguous GPU tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except ImportError:
+        pass
+    return 0
