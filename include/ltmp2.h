@@ -73,8 +73,12 @@ typedef struct {
   int n_fft;            /* grid points per axis; one of the compiled sizes     */
   double ecut;          /* orbital cutoff, Ha: every basis G has |G|^2/2 < ecut */
   double eaux;          /* auxiliary cutoff, Ha (inclusive)                     */
-  int n_pw;             /* basis size = number of states (all virtuals kept)    */
-  int n_occ;            /* occupied states, 1 <= n_occ < n_pw                   */
+  int n_pw;             /* plane-wave basis size                                */
+  int n_states;         /* states passed (occupied first, then virtual);
+                           0 means n_pw (all virtuals).  Passing a subset I of
+                           the occupied states plus all virtuals gives the
+                           energy restricted to i, j in I                       */
+  int n_occ;            /* occupied states, 1 <= n_occ < n_states               */
   int n_tau;            /* Laplace points, 1..16                                */
   int quad_mode;        /* ltmp2_quad_mode                                      */
   int prec;             /* ltmp2_precision                                      */
@@ -99,8 +103,8 @@ typedef struct {
  * the grid, computes and stores the overlap densities <a|e^{-iG.r}|j>
  * (Eq. SCHovrlp) and fixes the Laplace quadrature.
  *   miller [n_pw][3] int32   basis Miller indices (closed under m -> -m)
- *   eps    [n_pw]            orbital energies, ascending
- *   coeff  [n_pw][n_pw][2]   state-major coefficients c_p(G), (re, im)
+ *   eps    [n_states]        orbital energies, ascending
+ *   coeff  [n_states][n_pw][2]  state-major coefficients c_p(G), (re, im)
  *   tau, w [n_tau]           quadrature (only with LTMP2_QUAD_GIVEN, else NULL)
  *   mlp_weights              path of a weight file (LTMP2_QUAD_LEARNED), else NULL
  *   hip_stream               hipStream_t to run on (NULL: default stream)

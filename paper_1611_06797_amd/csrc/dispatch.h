@@ -18,7 +18,7 @@ bool grid_supported(int n);
 std::vector<int> supported_grids();
 
 struct GridOps {
-  ltmp2_status (*orbitals)(const cplx<double>* coef, int npw, SphereCols sc, double scale,
+  ltmp2_status (*orbitals)(const cplx<double>* coef, int nstates, int npw, SphereCols sc, double scale,
                            double* psi, long ld, hipStream_t st);
   ltmp2_status (*overlap)(const double* psi, long ld, int no, int nv, const int* gdesc, int nh,
                           int kmax, double dV, cplx<double>* nd, hipStream_t st);
@@ -42,9 +42,10 @@ const GridOps* grid_ops(int n);
   const GridOps* ops_ = grid_ops(n);      \
   if (!ops_) return LTMP2_EINVAL;
 
-inline ltmp2_status launch_orbitals(int n, const cplx<double>* coef, int npw, SphereCols sc,
-                                    double scale, double* psi, long ld, hipStream_t st) {
-  LTMP2_OPS_OR_FAIL(n) return ops_->orbitals(coef, npw, sc, scale, psi, ld, st);
+inline ltmp2_status launch_orbitals(int n, const cplx<double>* coef, int nstates, int npw,
+                                    SphereCols sc, double scale, double* psi, long ld,
+                                    hipStream_t st) {
+  LTMP2_OPS_OR_FAIL(n) return ops_->orbitals(coef, nstates, npw, sc, scale, psi, ld, st);
 }
 inline ltmp2_status launch_overlap(int n, const double* psi, long ld, int no, int nv,
                                    const int* gdesc, int nh, int kmax, double dV,

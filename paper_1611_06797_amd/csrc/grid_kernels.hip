@@ -40,10 +40,10 @@ ltmp2_status by_opt(int nout, auto&&... a) {
   return LTMP2_EINVAL;
 }
 
-ltmp2_status orbitals(const cplx<double>* coef, int npw, SphereCols sc, double scale, double* psi,
-                      long ld, hipStream_t st) {
+ltmp2_status orbitals(const cplx<double>* coef, int nstates, int npw, SphereCols sc, double scale,
+                      double* psi, long ld, hipStream_t st) {
   const int nk = 2 * sc.kmax + 1, sx = choose_sx(nk);
-  return launch(k_orbitals<double, N>, dim3(npw), slab_lds_bytes<double>(N, nk, sx), st, coef, npw,
+  return launch(k_orbitals<double, N>, dim3(nstates), slab_lds_bytes<double>(N, nk, sx), st, coef, npw,
                 sc, sx, scale, psi, ld);
 }
 

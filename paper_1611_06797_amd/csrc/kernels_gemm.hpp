@@ -12,7 +12,8 @@
 //              Green's-function rows.
 //
 // MFMA v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; accumulator element v of lane l is D[4 (l / 16) + v][l % 16].
+// B[l / 16][l % 16]; accumulator element v of lane l is D[(l / 16) + 4 v][l % 16]
+// (checked on gfx950 with a single-instruction probe).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(256) void k_gf_chi(const double* __restrict__ psi, 
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        Cs[wr * 32 + p * 16 + 4 * (lane >> 4) + v][wc * 32 + q * 16 + (lane & 15)] =
+        Cs[wr * 32 + p * 16 + (lane >> 4) + 4 * v][wc * 32 + q * 16 + (lane & 15)] =
             ao[p][q][v] * av[p][q][v];
   __syncthreads();
   for (int e = tid; e < GB_M * GB_N; e += 256) {
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void k_gemm_kmajor(const double* __restrict__ 
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const long m = m0 + wr * 32 + p * 16 + 4 * (lane >> 4) + v;
+        const long m = m0 + wr * 32 + p * 16 + (lane >> 4) + 4 * v;
         const long n = n0 + wc * 32 + q * 16 + (lane & 15);
         if (m < M && n < N) {
           const double s = rowscale ? rowscale[(m / rdiv) % rmod] : 1.0;

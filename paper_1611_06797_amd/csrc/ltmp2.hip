@@ -35,7 +35,7 @@ struct ltmp2_ctx {
   hipStream_t stream = nullptr;
 
   // sizes
-  int n = 0, nr = 0, npw = 0, no = 0, nv = 0, ng = 0, nh = 0, ntau = 0, npairs = 0;
+  int n = 0, nr = 0, npw = 0, nst = 0, no = 0, nv = 0, ng = 0, nh = 0, ntau = 0, npairs = 0;
   long nrp = 0;  // padded row stride of grid arrays (multiple of 64)
   int kmax_aux = 0, kmax_orb = 0, gblock = 0;
   double omega = 0, dV = 0, mu = 0, xmin = 0, xmax = 0, quad_delta = 0;
@@ -148,8 +148,10 @@ ltmp2_status validate(const ltmp2_params* p, const int32_t* miller, const double
   if (!(p->ecut > 0.0) || !std::isfinite(p->ecut) || !(p->eaux > 0.0) || !std::isfinite(p->eaux))
     return fail(nullptr, LTMP2_EINVAL, "ecut and eaux must be > 0");
   if (p->n_pw < 2) return fail(nullptr, LTMP2_EINVAL, "n_pw must be >= 2");
-  if (p->n_occ < 1 || p->n_occ >= p->n_pw)
-    return fail(nullptr, LTMP2_EINVAL, "n_occ must be in [1, n_pw - 1]");
+  const int nst = p->n_states ? p->n_states : p->n_pw;
+  if (nst < 2 || nst > p->n_pw) return fail(nullptr, LTMP2_EINVAL, "n_states must be in [2, n_pw]");
+  if (p->n_occ < 1 || p->n_occ >= nst)
+    return fail(nullptr, LTMP2_EINVAL, "n_occ must be in [1, n_states - 1]");
   if (p->n_tau < 1 || p->n_tau > 16) return fail(nullptr, LTMP2_EINVAL, "n_tau must be in [1, 16]");
   if (p->prec < 0 || p->prec > 2) return fail(nullptr, LTMP2_EINVAL, "unknown precision");
   if (p->quad_mode < 0 || p->quad_mode > 2) return fail(nullptr, LTMP2_EINVAL, "unknown quad_mode");
@@ -181,7 +183,7 @@ ltmp2_status validate(const ltmp2_params* p, const int32_t* miller, const double
   for (int k = 0; k < npw; ++k)
     if (!pos.count(std::make_tuple(-miller[3 * k], -miller[3 * k + 1], -miller[3 * k + 2])))
       return fail(nullptr, LTMP2_EINVAL, "basis not closed under G -> -G");
-  for (int k = 0; k < npw; ++k) {
+  for (int k = 0; k < nst; ++k) {
     if (!std::isfinite(eps[k])) return fail(nullptr, LTMP2_EINVAL, "non-finite orbital energy");
     if (k > 0 && eps[k] < eps[k - 1]) return fail(nullptr, LTMP2_EINVAL, "eps must be ascending");
   }
@@ -190,7 +192,7 @@ ltmp2_status validate(const ltmp2_params* p, const int32_t* miller, const double
   std::vector<int> negi(npw);
   for (int k = 0; k < npw; ++k)
     negi[k] = pos[std::make_tuple(-miller[3 * k], -miller[3 * k + 1], -miller[3 * k + 2])];
-  for (int s = 0; s < npw; ++s) {
+  for (int s = 0; s < nst; ++s) {
     const double* c = coeff + 2 * size_t(s) * npw;
     double nrm = 0.0, asym = 0.0;
     for (int k = 0; k < npw; ++k) {
@@ -287,15 +289,16 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
   c->nr = n * n * n;
   c->nrp = (c->nr + 63) / 64 * 64;
   c->npw = P.n_pw;
+  c->nst = P.n_states ? P.n_states : P.n_pw;
   c->no = P.n_occ;
-  c->nv = P.n_pw - P.n_occ;
+  c->nv = c->nst - P.n_occ;
   c->ntau = P.n_tau;
   c->omega = P.L * P.L * P.L;
   c->dV = c->omega / c->nr;
-  c->eps.assign(eps, eps + P.n_pw);
+  c->eps.assign(eps, eps + c->nst);
   c->mu = 0.5 * (eps[c->no - 1] + eps[c->no]);
   c->xmin = 2.0 * (eps[c->no] - eps[c->no - 1]);
-  c->xmax = 2.0 * (eps[P.n_pw - 1] - eps[0]);
+  c->xmax = 2.0 * (eps[c->nst - 1] - eps[0]);
   c->npairs = c->no * (c->no + 1) / 2;
   if (c->npairs > (1 << 22) || c->no >= (1 << 15))
     return fail(nullptr, LTMP2_EINVAL, "too many occupied states");
@@ -392,9 +395,9 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
     }
   }
   // coefficients in column order, and the real basis of the virtual ones
-  std::vector<double> coef_col(2 * size_t(c->npw) * c->npw);
+  std::vector<double> coef_col(2 * size_t(c->nst) * c->npw);
   std::vector<double> bpw(size_t(c->nv) * c->npw);
-  for (int s = 0; s < c->npw; ++s) {
+  for (int s = 0; s < c->nst; ++s) {
     const double* cs = coeff + 2 * size_t(s) * c->npw;
     for (int e = 0; e < c->npw; ++e) {
       coef_col[2 * (size_t(s) * c->npw + e)] = cs[2 * order[e]];
@@ -445,10 +448,10 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
 
   // device footprint and G'-block size
   const size_t nrp = c->nrp;
-  size_t fixed = sizeof(double) * (size_t(c->npw) * nrp + 2 * size_t(c->nv) * c->nh * c->no +
+  size_t fixed = sizeof(double) * (size_t(c->nst) * nrp + 2 * size_t(c->nv) * c->nh * c->no +
                                    size_t(c->nv) * c->npw + nrp * nrp + 2 * size_t(c->nh) * nrp +
                                    size_t(c->nh) + size_t(c->nh) * c->npairs) +
-                 sizeof(double) * 2 * size_t(c->npw) * c->npw;
+                 sizeof(double) * 2 * size_t(c->nst) * c->npw;
   const size_t per_g = sizeof(double) * (2 * size_t(c->no) * c->npw + 2 * size_t(c->no) * nrp);
   size_t budget = size_t(8) << 30;
   if (P.workspace_cap) {
@@ -470,7 +473,7 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
   c->sc = SphereCols{(int)cdesc.size(), ko, c->d_cdesc, c->d_cstart, c->d_ckx};
   double* d_coef = nullptr;
   if ((s = upload(c, &d_coef, coef_col))) return s;
-  if ((s = dalloc(c, &c->d_psi, size_t(c->npw) * nrp)) ||
+  if ((s = dalloc(c, &c->d_psi, size_t(c->nst) * nrp)) ||
       (s = dalloc(c, &c->d_nd, 2 * size_t(c->nv) * c->nh * c->no)) ||
       (s = dalloc(c, &c->d_chi, nrp * nrp)) || (s = dalloc(c, &c->d_chihat, 2 * size_t(c->nh) * nrp)) ||
       (s = dalloc(c, &c->d_pd, c->nh)) ||
@@ -481,11 +484,11 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
     return s;
   if (P.workspace_cap && c->bytes > P.workspace_cap)
     return fail(nullptr, LTMP2_ENOMEM, "device footprint exceeds the workspace cap");
-  HIPCHK(c, hipMemsetAsync(c->d_psi, 0, sizeof(double) * size_t(c->npw) * nrp, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_psi, 0, sizeof(double) * size_t(c->nst) * nrp, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_scal, 0, sizeof(double) * (2 * size_t(c->ntau) + 8), c->stream));
 
   // orbitals on the grid, then overlap densities (step (i))
-  if ((s = launch_orbitals(c->n, reinterpret_cast<const cplx<double>*>(d_coef), c->npw, c->sc,
+  if ((s = launch_orbitals(c->n, reinterpret_cast<const cplx<double>*>(d_coef), c->nst, c->npw, c->sc,
                            1.0 / std::sqrt(c->omega), c->d_psi, c->nrp, c->stream)))
     return fail(nullptr, s, "orbital synthesis launch failed");
   if ((s = launch_overlap(c->n, c->d_psi, c->nrp, c->no, c->nv, c->d_gdesc, c->nh, c->kmax_aux,

@@ -29,7 +29,8 @@ STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "red
 
 class Params(C.Structure):
     _fields_ = [("L", C.c_double), ("n_fft", C.c_int), ("ecut", C.c_double),
-                ("eaux", C.c_double), ("n_pw", C.c_int), ("n_occ", C.c_int),
+                ("eaux", C.c_double), ("n_pw", C.c_int), ("n_states", C.c_int),
+                ("n_occ", C.c_int),
                 ("n_tau", C.c_int), ("quad_mode", C.c_int), ("prec", C.c_int),
                 ("workspace_cap", C.c_size_t)]
 
@@ -134,7 +135,7 @@ class Context:
         tau_a = None if tau is None else np.ascontiguousarray(tau, np.float64)
         w_a = None if w is None else np.ascontiguousarray(w, np.float64)
         p = Params(float(L), int(n_fft), float(ecut), float(eaux), int(miller.shape[0]),
-                   int(n_occ), int(n_tau), int(quad_mode), int(prec), int(workspace_cap))
+                   int(eps.shape[0]), int(n_occ), int(n_tau), int(quad_mode), int(prec), int(workspace_cap))
         if stream is None:
             stream = _current_stream()
         self._ctx = C.c_void_p()
