@@ -7,6 +7,7 @@
 
 #include "../../include/ltmp2.h"
 #include "kernels_fft.hpp"
+#include "modes.h"
 
 namespace ltmp2 {
 
@@ -17,70 +18,39 @@ inline int max_outputs() { return kMaxOpt * kThreads; }
 bool grid_supported(int n);
 std::vector<int> supported_grids();
 
+template <class T>
 struct GridOps {
-  ltmp2_status (*orbitals)(const cplx<double>* coef, int nstates, int npw, SphereCols sc, double scale,
-                           double* psi, long ld, hipStream_t st);
-  ltmp2_status (*overlap)(const double* psi, long ld, int no, int nv, const int* gdesc, int nh,
-                          int kmax, double dV, cplx<double>* nd, hipStream_t st);
-  ltmp2_status (*chi_rows)(const double* chi, long ld, int nr, const int* gdesc, int nh, int kmax,
-                           double dV, cplx<double>* chihat, hipStream_t st);
-  ltmp2_status (*chi_cols)(const cplx<double>* chihat, long ld, const int* gdesc, int ng, int nh,
+  ltmp2_status (*orbitals)(const cplx<double>* coef, int nstates, int npw, SphereCols sc,
+                           double scale, T* psi, long ld, hipStream_t st);
+  ltmp2_status (*overlap)(const T* psi, long ld, int no, int nv, const int* gdesc, int nh,
+                          int kmax, double dV, cplx<T>* nd, hipStream_t st);
+  ltmp2_status (*chi_rows)(const T* chi, long ld, int nr, const int* gdesc, int nh, int kmax,
+                           double dV, cplx<T>* chihat, hipStream_t st);
+  ltmp2_status (*chi_cols)(const cplx<T>* chihat, long ld, const int* gdesc, int ng, int nh,
                            const double* v, int kmax, double dV, double* pd,
                            cplx<double>* chi_out, hipStream_t st);
-  ltmp2_status (*wstates)(const double* P, int npw, const int* wq, const signed char* wsgn,
-                          SphereCols sc, int nitems, double scale, cplx<double>* w, long ld,
+  ltmp2_status (*wstates)(const T* P, int npw, const int* wq, const signed char* wsgn,
+                          SphereCols sc, int nitems, double scale, cplx<T>* w, long ld,
                           hipStream_t st);
-  ltmp2_status (*pair)(const double* psi, long ld, const cplx<double>* w, int no,
-                       const int* pairs, int npairs, int gb, const int* gdesc, int ng,
-                       const double* v, int kmax, double dV2, double* xpart, hipStream_t st);
+  ltmp2_status (*pair)(const T* psi, long ld, const cplx<T>* w, int no, const int* pairs,
+                       int npairs, int gb, const int* gdesc, int ng, const double* v, int kmax,
+                       double dV2, double* xpart, hipStream_t st);
 };
 
-const GridOps* grid_ops(int n);
+template <class T>
+const GridOps<T>* grid_ops(int n);
 
-// Convenience wrappers used by the host driver.
-#define LTMP2_OPS_OR_FAIL(n)              \
-  const GridOps* ops_ = grid_ops(n);      \
-  if (!ops_) return LTMP2_EINVAL;
+// Matrix-core contractions (instantiated in registry.hip, see kernels_gemm.hpp).
+template <int MODE>
+ltmp2_status launch_gf_chi(const void* psi, long ld, int no, int nv, const double* fo,
+                           const double* fv, void* chi, long ldc, long ntiles, hipStream_t st);
+template <int MODE>
+ltmp2_status launch_gemm_kmajor(const void* A, long lda, const void* B, long ldb, void* C,
+                                long ldc, int M, int N, int K, const double* sk,
+                                const double* rowscale, int rdiv, int rmod, hipStream_t st);
 
-inline ltmp2_status launch_orbitals(int n, const cplx<double>* coef, int nstates, int npw,
-                                    SphereCols sc, double scale, double* psi, long ld,
-                                    hipStream_t st) {
-  LTMP2_OPS_OR_FAIL(n) return ops_->orbitals(coef, nstates, npw, sc, scale, psi, ld, st);
-}
-inline ltmp2_status launch_overlap(int n, const double* psi, long ld, int no, int nv,
-                                   const int* gdesc, int nh, int kmax, double dV,
-                                   cplx<double>* nd, hipStream_t st) {
-  LTMP2_OPS_OR_FAIL(n) return ops_->overlap(psi, ld, no, nv, gdesc, nh, kmax, dV, nd, st);
-}
-inline ltmp2_status launch_chi_rows(int n, const double* chi, long ld, int nr, const int* gdesc,
-                                    int nh, int kmax, double dV, cplx<double>* chihat,
-                                    hipStream_t st) {
-  LTMP2_OPS_OR_FAIL(n) return ops_->chi_rows(chi, ld, nr, gdesc, nh, kmax, dV, chihat, st);
-}
-inline ltmp2_status launch_chi_cols(int n, const cplx<double>* chihat, long ld, const int* gdesc,
-                                    int ng, int nh, const double* v, int kmax, double dV,
-                                    double* pd, cplx<double>* chi_out, hipStream_t st) {
-  LTMP2_OPS_OR_FAIL(n) return ops_->chi_cols(chihat, ld, gdesc, ng, nh, v, kmax, dV, pd, chi_out, st);
-}
-inline ltmp2_status launch_wstates(int n, const double* P, int npw, const int* wq,
-                                   const signed char* wsgn, SphereCols sc, int nitems,
-                                   double scale, cplx<double>* w, long ld, hipStream_t st) {
-  LTMP2_OPS_OR_FAIL(n) return ops_->wstates(P, npw, wq, wsgn, sc, nitems, scale, w, ld, st);
-}
-inline ltmp2_status launch_pair(int n, const double* psi, long ld, const cplx<double>* w, int no,
-                                const int* pairs, int npairs, int gb, const int* gdesc, int ng,
-                                const double* v, int kmax, double dV2, double* xpart,
-                                hipStream_t st) {
-  LTMP2_OPS_OR_FAIL(n) return ops_->pair(psi, ld, w, no, pairs, npairs, gb, gdesc, ng, v, kmax,
-                                         dV2, xpart, st);
-}
-
-// Matrix-core contractions (defined in registry.hip, see kernels_gemm.hpp).
-__global__ void k_gf_chi(const double* psi, long ld, int no, int nv, const double* fo,
-                         const double* fv, double* chi, long ldc);
-__global__ void k_gemm_kmajor(const double* A, long lda, const double* B, long ldb, double* C,
-                              long ldc, int M, int N, int K, const double* sk,
-                              const double* rowscale, int rdiv, int rmod);
+// float -> double copy (diagnostic outputs of FP32 contexts)
+__global__ void k_widen(const float* in, double* out, long n);
 
 // Deterministic single-block reductions of the per-G' partial sums.
 //   E_d(tau) = -4 sum_{g in H} pd[g]        (pd includes v(G'); G' and -G')

@@ -35,7 +35,7 @@ LT_HD cplx<T> csub(cplx<T> a, cplx<T> b) {
 }
 template <class T>
 LT_HD cplx<T> cfma(cplx<T> a, cplx<T> b, cplx<T> acc) {
-  return {fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y))};
+  return {acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x};
 }
 
 // ---- compile-time trigonometry ---------------------------------------------

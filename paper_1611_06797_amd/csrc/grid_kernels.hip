@@ -13,9 +13,10 @@ namespace {
 constexpr int N = LTMP2_N;
 constexpr size_t kLdsCap = 150 * 1024;
 
+template <class T>
 int choose_sx(int nk) {
   int sx = std::min(N, 8);
-  while (sx > 1 && slab_lds_bytes<double>(N, nk, sx) > kLdsCap) --sx;
+  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) > kLdsCap) --sx;
   return sx;
 }
 
@@ -40,91 +41,135 @@ ltmp2_status by_opt(int nout, auto&&... a) {
   return LTMP2_EINVAL;
 }
 
+template <class T>
 ltmp2_status orbitals(const cplx<double>* coef, int nstates, int npw, SphereCols sc, double scale,
-                      double* psi, long ld, hipStream_t st) {
-  const int nk = 2 * sc.kmax + 1, sx = choose_sx(nk);
-  return launch(k_orbitals<double, N>, dim3(nstates), slab_lds_bytes<double>(N, nk, sx), st, coef, npw,
-                sc, sx, scale, psi, ld);
+                      T* psi, long ld, hipStream_t st) {
+  const int nk = 2 * sc.kmax + 1, sx = choose_sx<T>(nk);
+  return launch(k_orbitals<T, N>, dim3(nstates), slab_lds_bytes<T>(N, nk, sx), st, coef, npw, sc,
+                sx, scale, psi, ld);
 }
 
-template <int OPT>
+template <class T>
 struct OverlapF {
-  static ltmp2_status go(const double* psi, long ld, int no, int nv, const int* gdesc, int nh,
-                         int kmax, double dV, cplx<double>* nd, hipStream_t st) {
-    constexpr int NF = 4;
-    const int nk = 2 * kmax + 1, sx = choose_sx(nk);
-    return launch(k_overlap<double, N, NF, OPT>, dim3((no + NF - 1) / NF, nv),
-                  slab_lds_bytes<double>(N, nk, sx), st, psi, ld, no, gdesc, nh, kmax, sx, dV, nd);
-  }
+  template <int OPT>
+  struct F {
+    static ltmp2_status go(const T* psi, long ld, int no, int nv, const int* gdesc, int nh,
+                           int kmax, double dV, cplx<T>* nd, hipStream_t st) {
+      constexpr int NF = 4;
+      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
+      return launch(k_overlap<T, N, NF, OPT>, dim3((no + NF - 1) / NF, nv),
+                    slab_lds_bytes<T>(N, nk, sx), st, psi, ld, no, gdesc, nh, kmax, sx, dV, nd);
+    }
+  };
 };
-ltmp2_status overlap(const double* psi, long ld, int no, int nv, const int* gdesc, int nh,
-                     int kmax, double dV, cplx<double>* nd, hipStream_t st) {
-  return by_opt<OverlapF>(nh, psi, ld, no, nv, gdesc, nh, kmax, dV, nd, st);
+template <class T>
+ltmp2_status overlap(const T* psi, long ld, int no, int nv, const int* gdesc, int nh, int kmax,
+                     double dV, cplx<T>* nd, hipStream_t st) {
+  return by_opt<OverlapF<T>::template F>(nh, psi, ld, no, nv, gdesc, nh, kmax, dV, nd, st);
 }
 
-template <int OPT>
+template <class T>
 struct ChiRowsF {
-  static ltmp2_status go(const double* chi, long ld, int nr, const int* gdesc, int nh, int kmax,
-                         double dV, cplx<double>* chihat, hipStream_t st) {
-    constexpr int NF = 2;
-    const int nk = 2 * kmax + 1, sx = choose_sx(nk);
-    return launch(k_chi_rows<double, N, NF, OPT>, dim3((nr + NF - 1) / NF),
-                  slab_lds_bytes<double>(N, nk, sx), st, chi, ld, nr, gdesc, nh, kmax, sx, dV,
-                  chihat);
-  }
+  template <int OPT>
+  struct F {
+    static ltmp2_status go(const T* chi, long ld, int nr, const int* gdesc, int nh, int kmax,
+                           double dV, cplx<T>* chihat, hipStream_t st) {
+      constexpr int NF = 2;
+      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
+      return launch(k_chi_rows<T, N, NF, OPT>, dim3((nr + NF - 1) / NF),
+                    slab_lds_bytes<T>(N, nk, sx), st, chi, ld, nr, gdesc, nh, kmax, sx, dV,
+                    chihat);
+    }
+  };
 };
-ltmp2_status chi_rows(const double* chi, long ld, int nr, const int* gdesc, int nh, int kmax,
-                      double dV, cplx<double>* chihat, hipStream_t st) {
-  return by_opt<ChiRowsF>(nh, chi, ld, nr, gdesc, nh, kmax, dV, chihat, st);
+template <class T>
+ltmp2_status chi_rows(const T* chi, long ld, int nr, const int* gdesc, int nh, int kmax, double dV,
+                      cplx<T>* chihat, hipStream_t st) {
+  return by_opt<ChiRowsF<T>::template F>(nh, chi, ld, nr, gdesc, nh, kmax, dV, chihat, st);
 }
 
-template <int OPT>
+template <class T>
 struct ChiColsF {
-  static ltmp2_status go(const cplx<double>* chihat, long ld, const int* gdesc, int ng, int nh,
-                         const double* v, int kmax, double dV, double* pd, cplx<double>* chi_out,
-                         hipStream_t st) {
-    const int nk = 2 * kmax + 1, sx = choose_sx(nk);
-    return launch(k_chi_cols<double, N, OPT>, dim3(nh), slab_lds_bytes<double>(N, nk, sx), st,
-                  chihat, ld, gdesc, ng, nh, v, kmax, sx, dV, pd, chi_out);
-  }
+  template <int OPT>
+  struct F {
+    static ltmp2_status go(const cplx<T>* chihat, long ld, const int* gdesc, int ng, int nh,
+                           const double* v, int kmax, double dV, double* pd,
+                           cplx<double>* chi_out, hipStream_t st) {
+      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
+      return launch(k_chi_cols<T, N, OPT>, dim3(nh), slab_lds_bytes<T>(N, nk, sx), st, chihat, ld,
+                    gdesc, ng, nh, v, kmax, sx, dV, pd, chi_out);
+    }
+  };
 };
-ltmp2_status chi_cols(const cplx<double>* chihat, long ld, const int* gdesc, int ng, int nh,
+template <class T>
+ltmp2_status chi_cols(const cplx<T>* chihat, long ld, const int* gdesc, int ng, int nh,
                       const double* v, int kmax, double dV, double* pd, cplx<double>* chi_out,
                       hipStream_t st) {
-  return by_opt<ChiColsF>(ng, chihat, ld, gdesc, ng, nh, v, kmax, dV, pd, chi_out, st);
+  return by_opt<ChiColsF<T>::template F>(ng, chihat, ld, gdesc, ng, nh, v, kmax, dV, pd, chi_out,
+                                         st);
 }
 
-ltmp2_status wstates(const double* P, int npw, const int* wq, const signed char* wsgn,
-                     SphereCols sc, int nitems, double scale, cplx<double>* w, long ld,
-                     hipStream_t st) {
-  const int nk = 2 * sc.kmax + 1, sx = choose_sx(nk);
-  return launch(k_wstates<double, N>, dim3(nitems), slab_lds_bytes<double>(N, nk, sx), st, P, npw,
-                wq, wsgn, sc, sx, scale, w, ld);
+template <class T>
+ltmp2_status wstates(const T* P, int npw, const int* wq, const signed char* wsgn, SphereCols sc,
+                     int nitems, double scale, cplx<T>* w, long ld, hipStream_t st) {
+  const int nk = 2 * sc.kmax + 1, sx = choose_sx<T>(nk);
+  return launch(k_wstates<T, N>, dim3(nitems), slab_lds_bytes<T>(N, nk, sx), st, P, npw, wq, wsgn,
+                sc, sx, scale, w, ld);
 }
 
-template <int OPT>
+template <class T>
 struct PairF {
-  static ltmp2_status go(const double* psi, long ld, const cplx<double>* w, int no,
-                         const int* pairs, int npairs, int gb, const int* gdesc, int ng,
-                         const double* v, int kmax, double dV2, double* xpart, hipStream_t st) {
-    const int nk = 2 * kmax + 1, sx = choose_sx(nk);
-    return launch(k_pair<double, N, OPT>, dim3(npairs, gb), slab_lds_bytes<double>(N, nk, sx), st,
-                  psi, ld, w, no, pairs, npairs, gdesc, ng, v, kmax, sx, dV2, xpart);
-  }
+  template <int OPT>
+  struct F {
+    static ltmp2_status go(const T* psi, long ld, const cplx<T>* w, int no, const int* pairs,
+                           int npairs, int gb, const int* gdesc, int ng, const double* v, int kmax,
+                           double dV2, double* xpart, hipStream_t st) {
+      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
+      return launch(k_pair<T, N, OPT>, dim3(npairs, gb), slab_lds_bytes<T>(N, nk, sx), st, psi, ld,
+                    w, no, pairs, npairs, gdesc, ng, v, kmax, sx, dV2, xpart);
+    }
+  };
 };
-ltmp2_status pair(const double* psi, long ld, const cplx<double>* w, int no, const int* pairs,
-                  int npairs, int gb, const int* gdesc, int ng, const double* v, int kmax,
-                  double dV2, double* xpart, hipStream_t st) {
-  return by_opt<PairF>(ng, psi, ld, w, no, pairs, npairs, gb, gdesc, ng, v, kmax, dV2, xpart, st);
+template <class T>
+ltmp2_status pair(const T* psi, long ld, const cplx<T>* w, int no, const int* pairs, int npairs,
+                  int gb, const int* gdesc, int ng, const double* v, int kmax, double dV2,
+                  double* xpart, hipStream_t st) {
+  return by_opt<PairF<T>::template F>(ng, psi, ld, w, no, pairs, npairs, gb, gdesc, ng, v, kmax,
+                                      dV2, xpart, st);
 }
+
+// Explicit instantiation in both compilation passes, so the device pass
+// instantiates every kernel the host launchers reference.
+#define LTMP2_INST(T)                                                                          \
+  template ltmp2_status orbitals<T>(const cplx<double>*, int, int, SphereCols, double, T*, long, \
+                                    hipStream_t);                                              \
+  template ltmp2_status overlap<T>(const T*, long, int, int, const int*, int, int, double,     \
+                                   cplx<T>*, hipStream_t);                                     \
+  template ltmp2_status chi_rows<T>(const T*, long, int, const int*, int, int, double, cplx<T>*, \
+                                    hipStream_t);                                              \
+  template ltmp2_status chi_cols<T>(const cplx<T>*, long, const int*, int, int, const double*, \
+                                    int, double, double*, cplx<double>*, hipStream_t);         \
+  template ltmp2_status wstates<T>(const T*, int, const int*, const signed char*, SphereCols,   \
+                                   int, double, cplx<T>*, long, hipStream_t);                  \
+  template ltmp2_status pair<T>(const T*, long, const cplx<T>*, int, const int*, int, int,     \
+                                const int*, int, const double*, int, double, double*,          \
+                                hipStream_t);
+LTMP2_INST(double)
+LTMP2_INST(float)
 
 }  // namespace
 
 #define LTMP2_CAT2(a, b) a##b
 #define LTMP2_CAT(a, b) LTMP2_CAT2(a, b)
 #if !defined(__HIP_DEVICE_COMPILE__)
-extern const GridOps LTMP2_CAT(kGridOps_, LTMP2_N);
-const GridOps LTMP2_CAT(kGridOps_, LTMP2_N) = {orbitals, overlap, chi_rows, chi_cols, wstates, pair};
+extern const GridOps<double> LTMP2_CAT(kGridOpsD_, LTMP2_N);
+extern const GridOps<float> LTMP2_CAT(kGridOpsF_, LTMP2_N);
+const GridOps<double> LTMP2_CAT(kGridOpsD_, LTMP2_N) = {
+    orbitals<double>, overlap<double>, chi_rows<double>, chi_cols<double>, wstates<double>,
+    pair<double>};
+const GridOps<float> LTMP2_CAT(kGridOpsF_, LTMP2_N) = {
+    orbitals<float>, overlap<float>, chi_rows<float>, chi_cols<float>, wstates<float>,
+    pair<float>};
 #endif
 
 }  // namespace ltmp2

@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict
 // and the sign s = +1 for G_k, -1 for -G_k (c_a(-G) = conj c_a(G)):
 //   W(G) = (P_re[q_re] - s P_im[q_im]) + i (P_im[q_re] + s P_re[q_im]).
 template <class T, int N>
-__global__ __launch_bounds__(kThreads) void k_wstates(const double* __restrict__ P, int npw,
+__global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, int npw,
                                                       const int* __restrict__ wq,
                                                       const signed char* __restrict__ wsgn,
                                                       SphereCols sc, int sx, double scale,
@@ -192,14 +192,14 @@ __global__ __launch_bounds__(kThreads) void k_wstates(const double* __restrict__
   for (int e = threadIdx.x; e < sx * nk * nk; e += kThreads) L.t2[e] = {T(0), T(0)};
   __syncthreads();
   const long item = blockIdx.x;
-  const double* pre = P + (2 * item) * long(npw);
-  const double* pim = pre + npw;
+  const T* pre = P + (2 * item) * long(npw);
+  const T* pim = pre + npw;
   cplx<T>* out = w + item * ld;
   auto cf = [&](int, int e) {
     const int q = wq[e];
     const int qr = q & 0xffff, qi = (q >> 16) - 1;
-    const double s = wsgn[e];
-    double re = pre[qr], im = pim[qr];
+    const T s = T(wsgn[e]);
+    T re = pre[qr], im = pim[qr];
     if (qi >= 0) {
       re -= s * pim[qi];
       im += s * pre[qi];

@@ -55,15 +55,16 @@ struct ltmp2_ctx {
   double* d_fo = nullptr;  // [ntau][no]
   double* d_fv = nullptr;  // [ntau][nv]
 
-  // device data
-  double* d_psi = nullptr;     // [npw][nrp]
-  double* d_nd = nullptr;      // [nv][nh][no] complex
-  double* d_bpw = nullptr;     // [nv][npw] real basis of virtual coefficients
-  double* d_chi = nullptr;     // [nrp][nrp]
-  double* d_chihat = nullptr;  // [nh][nrp] complex
+  // device data, element type double (FP64) or float (FP32, BF16X3)
+  size_t esz = sizeof(double);
+  void* d_psi = nullptr;       // [nst][nrp]
+  void* d_nd = nullptr;        // [nv][nh][no] complex
+  void* d_bpw = nullptr;       // [nv][npw] real basis of virtual coefficients
+  void* d_chi = nullptr;       // [nrp][nrp]
+  void* d_chihat = nullptr;    // [nh][nrp] complex
   double* d_pd = nullptr;      // [nh]
-  double* d_P = nullptr;       // [gblock * no * 2][npw]
-  double* d_w = nullptr;       // [gblock * no][nrp] complex
+  void* d_P = nullptr;         // [gblock * no * 2][npw]
+  void* d_w = nullptr;         // [gblock * no][nrp] complex
   double* d_xpart = nullptr;   // [nh][npairs]
   double* d_scal = nullptr;    // [2 * ntau + 8] device scalars
 
@@ -128,6 +129,19 @@ ltmp2_status dalloc(ltmp2_ctx* c, T** p, size_t count) {
   return LTMP2_OK;
 }
 
+ltmp2_status dalloc_bytes(ltmp2_ctx* c, void** p, size_t bytes) {
+  void* q = nullptr;
+  const size_t b = std::max<size_t>(bytes, 1);
+  hipError_t e = hipMalloc(&q, b);
+  if (e != hipSuccess)
+    return fail(c, e == hipErrorOutOfMemory ? LTMP2_ENOMEM : LTMP2_EDEVICE,
+                "hipMalloc(" + std::to_string(b) + " bytes): " + hipGetErrorString(e));
+  c->owned.push_back(q);
+  c->bytes += b;
+  *p = q;
+  return LTMP2_OK;
+}
+
 template <class T>
 ltmp2_status upload(ltmp2_ctx* c, T** p, const std::vector<T>& v) {
   ltmp2_status s = dalloc(c, p, v.size());
@@ -155,8 +169,6 @@ ltmp2_status validate(const ltmp2_params* p, const int32_t* miller, const double
   if (p->n_tau < 1 || p->n_tau > 16) return fail(nullptr, LTMP2_EINVAL, "n_tau must be in [1, 16]");
   if (p->prec < 0 || p->prec > 2) return fail(nullptr, LTMP2_EINVAL, "unknown precision");
   if (p->quad_mode < 0 || p->quad_mode > 2) return fail(nullptr, LTMP2_EINVAL, "unknown quad_mode");
-  if (p->prec != LTMP2_FP64)
-    return fail(nullptr, LTMP2_EINVAL, "only LTMP2_FP64 is available in this build");
   if (p->quad_mode == LTMP2_QUAD_LEARNED)
     return fail(nullptr, LTMP2_EINVAL, "learned quadrature is not available in this build");
   if (!miller || !eps || !coeff) return fail(nullptr, LTMP2_EINVAL, "NULL input array");
@@ -280,6 +292,20 @@ extern "C" int ltmp2_supported_grids(int* sizes, int cap) {
 }
 
 namespace {
+
+template <class T>
+ltmp2_status prepare_cell(ltmp2_ctx* c, const cplx<double>* d_coef) {
+  const GridOps<T>* ops = grid_ops<T>(c->n);
+  if (!ops) return fail(nullptr, LTMP2_EINVAL, "grid not compiled");
+  ltmp2_status s;
+  if ((s = ops->orbitals(d_coef, c->nst, c->npw, c->sc, 1.0 / std::sqrt(c->omega),
+                         static_cast<T*>(c->d_psi), c->nrp, c->stream)))
+    return fail(nullptr, s, "orbital synthesis launch failed");
+  if ((s = ops->overlap(static_cast<const T*>(c->d_psi), c->nrp, c->no, c->nv, c->d_gdesc, c->nh,
+                        c->kmax_aux, c->dV, static_cast<cplx<T>*>(c->d_nd), c->stream)))
+    return fail(nullptr, s, "overlap-density launch failed");
+  return LTMP2_OK;
+}
 
 ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
                         const double* coeff, const double* tau, const double* w) {
@@ -448,11 +474,13 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
 
   // device footprint and G'-block size
   const size_t nrp = c->nrp;
-  size_t fixed = sizeof(double) * (size_t(c->nst) * nrp + 2 * size_t(c->nv) * c->nh * c->no +
-                                   size_t(c->nv) * c->npw + nrp * nrp + 2 * size_t(c->nh) * nrp +
-                                   size_t(c->nh) + size_t(c->nh) * c->npairs) +
+  c->esz = (P.prec == LTMP2_FP64) ? sizeof(double) : sizeof(float);
+  const size_t es = c->esz;
+  size_t fixed = es * (size_t(c->nst) * nrp + 2 * size_t(c->nv) * c->nh * c->no +
+                       size_t(c->nv) * c->npw + nrp * nrp + 2 * size_t(c->nh) * nrp) +
+                 sizeof(double) * (size_t(c->nh) + size_t(c->nh) * c->npairs) +
                  sizeof(double) * 2 * size_t(c->nst) * c->npw;
-  const size_t per_g = sizeof(double) * (2 * size_t(c->no) * c->npw + 2 * size_t(c->no) * nrp);
+  const size_t per_g = es * (2 * size_t(c->no) * c->npw + 2 * size_t(c->no) * nrp);
   size_t budget = size_t(8) << 30;
   if (P.workspace_cap) {
     if (fixed + per_g > P.workspace_cap)
@@ -467,33 +495,41 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
       (s = upload(c, &c->d_ckx, ckx)) || (s = upload(c, &c->d_wq, wq)) ||
       (s = upload(c, &c->d_wsgn, wsgn)) || (s = upload(c, &c->d_gdesc, gdesc)) ||
       (s = upload(c, &c->d_pairs, pairs)) || (s = upload(c, &c->d_v, v)) ||
-      (s = upload(c, &c->d_fo, fo)) || (s = upload(c, &c->d_fv, fv)) ||
-      (s = upload(c, &c->d_bpw, bpw)))
+      (s = upload(c, &c->d_fo, fo)) || (s = upload(c, &c->d_fv, fv)))
     return s;
+  if (es == sizeof(double)) {
+    double* d = nullptr;
+    if ((s = upload(c, &d, bpw))) return s;
+    c->d_bpw = d;
+  } else {
+    std::vector<float> bf(bpw.begin(), bpw.end());
+    float* d = nullptr;
+    if ((s = upload(c, &d, bf))) return s;
+    c->d_bpw = d;
+  }
   c->sc = SphereCols{(int)cdesc.size(), ko, c->d_cdesc, c->d_cstart, c->d_ckx};
   double* d_coef = nullptr;
   if ((s = upload(c, &d_coef, coef_col))) return s;
-  if ((s = dalloc(c, &c->d_psi, size_t(c->nst) * nrp)) ||
-      (s = dalloc(c, &c->d_nd, 2 * size_t(c->nv) * c->nh * c->no)) ||
-      (s = dalloc(c, &c->d_chi, nrp * nrp)) || (s = dalloc(c, &c->d_chihat, 2 * size_t(c->nh) * nrp)) ||
+  if ((s = dalloc_bytes(c, &c->d_psi, es * size_t(c->nst) * nrp)) ||
+      (s = dalloc_bytes(c, &c->d_nd, es * 2 * size_t(c->nv) * c->nh * c->no)) ||
+      (s = dalloc_bytes(c, &c->d_chi, es * nrp * nrp)) ||
+      (s = dalloc_bytes(c, &c->d_chihat, es * 2 * size_t(c->nh) * nrp)) ||
       (s = dalloc(c, &c->d_pd, c->nh)) ||
-      (s = dalloc(c, &c->d_P, 2 * size_t(c->gblock) * c->no * c->npw)) ||
-      (s = dalloc(c, &c->d_w, 2 * size_t(c->gblock) * c->no * nrp)) ||
+      (s = dalloc_bytes(c, &c->d_P, es * 2 * size_t(c->gblock) * c->no * c->npw)) ||
+      (s = dalloc_bytes(c, &c->d_w, es * 2 * size_t(c->gblock) * c->no * nrp)) ||
       (s = dalloc(c, &c->d_xpart, size_t(c->nh) * c->npairs)) ||
       (s = dalloc(c, &c->d_scal, 2 * size_t(c->ntau) + 8)))
     return s;
   if (P.workspace_cap && c->bytes > P.workspace_cap)
     return fail(nullptr, LTMP2_ENOMEM, "device footprint exceeds the workspace cap");
-  HIPCHK(c, hipMemsetAsync(c->d_psi, 0, sizeof(double) * size_t(c->nst) * nrp, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_psi, 0, es * size_t(c->nst) * nrp, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_scal, 0, sizeof(double) * (2 * size_t(c->ntau) + 8), c->stream));
 
   // orbitals on the grid, then overlap densities (step (i))
-  if ((s = launch_orbitals(c->n, reinterpret_cast<const cplx<double>*>(d_coef), c->nst, c->npw, c->sc,
-                           1.0 / std::sqrt(c->omega), c->d_psi, c->nrp, c->stream)))
-    return fail(nullptr, s, "orbital synthesis launch failed");
-  if ((s = launch_overlap(c->n, c->d_psi, c->nrp, c->no, c->nv, c->d_gdesc, c->nh, c->kmax_aux,
-                          c->dV, reinterpret_cast<cplx<double>*>(c->d_nd), c->stream)))
-    return fail(nullptr, s, "overlap-density launch failed");
+  s = (es == sizeof(double))
+          ? prepare_cell<double>(c, reinterpret_cast<const cplx<double>*>(d_coef))
+          : prepare_cell<float>(c, reinterpret_cast<const cplx<double>*>(d_coef));
+  if (s) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LTMP2_OK;
 }
@@ -506,28 +542,30 @@ ltmp2_status usable(ltmp2_ctx* c, int itau) {
 }
 
 // direct term at one Laplace point; value left in d_scal[2 * itau]
-ltmp2_status run_direct(ltmp2_ctx* c, int itau, double* chi_out) {
+template <class T, int MODE>
+ltmp2_status run_direct_t(ltmp2_ctx* c, int itau, double* chi_out) {
   ltmp2_status s;
+  const GridOps<T>* ops = grid_ops<T>(c->n);
   const double* fo = c->d_fo + size_t(itau) * c->no;
   const double* fv = c->d_fv + size_t(itau) * c->nv;
-  const int nt = int(c->nrp / 64);
+  const long nt = c->nrp / 64;
   {
-  StageTimer tm(c, 0);
-  hipLaunchKernelGGL(k_gf_chi, dim3(unsigned(long(nt) * (nt + 1) / 2)), dim3(256), 0, c->stream,
-                     c->d_psi, c->nrp, c->no, c->nv, fo, fv, c->d_chi, c->nrp);
+    StageTimer tm(c, 0);
+    s = launch_gf_chi<MODE>(c->d_psi, c->nrp, c->no, c->nv, fo, fv, c->d_chi, c->nrp,
+                            nt * (nt + 1) / 2, c->stream);
   }
-  if ((s = check_launch(c, "k_gf_chi"))) return s;
+  if (s) return fail(c, s, "chi tile launch failed");
   {
-  StageTimer tm(c, 1);
-  s = launch_chi_rows(c->n, c->d_chi, c->nrp, c->nr, c->d_gdesc, c->nh, c->kmax_aux, c->dV,
-                           reinterpret_cast<cplx<double>*>(c->d_chihat), c->stream);
+    StageTimer tm(c, 1);
+    s = ops->chi_rows(static_cast<const T*>(c->d_chi), c->nrp, c->nr, c->d_gdesc, c->nh,
+                      c->kmax_aux, c->dV, static_cast<cplx<T>*>(c->d_chihat), c->stream);
   }
   if (s) return fail(c, s, "chi row transform launch failed");
   {
-  StageTimer tm(c, 2);
-  s = launch_chi_cols(c->n, reinterpret_cast<const cplx<double>*>(c->d_chihat), c->nrp,
-                           c->d_gdesc, c->ng, c->nh, c->d_v, c->kmax_aux, c->dV, c->d_pd,
-                           reinterpret_cast<cplx<double>*>(chi_out), c->stream);
+    StageTimer tm(c, 2);
+    s = ops->chi_cols(static_cast<const cplx<T>*>(c->d_chihat), c->nrp, c->d_gdesc, c->ng, c->nh,
+                      c->d_v, c->kmax_aux, c->dV, c->d_pd,
+                      reinterpret_cast<cplx<double>*>(chi_out), c->stream);
   }
   if (s) return fail(c, s, "chi column transform launch failed");
   StageTimer tm(c, 6);
@@ -536,9 +574,19 @@ ltmp2_status run_direct(ltmp2_ctx* c, int itau, double* chi_out) {
   return check_launch(c, "k_reduce_direct");
 }
 
+ltmp2_status run_direct(ltmp2_ctx* c, int itau, double* chi_out) {
+  switch (c->prm.prec) {
+    case LTMP2_FP64: return run_direct_t<double, kF64>(c, itau, chi_out);
+    case LTMP2_FP32: return run_direct_t<float, kF32>(c, itau, chi_out);
+    default: return run_direct_t<float, kBF16x3>(c, itau, chi_out);
+  }
+}
+
 // exchange term at one Laplace point for G' in H[g_first, g_first + g_count)
-ltmp2_status run_exchange(ltmp2_ctx* c, int itau, int g_first, int g_count) {
+template <class T, int MODE>
+ltmp2_status run_exchange_t(ltmp2_ctx* c, int itau, int g_first, int g_count) {
   ltmp2_status s;
+  const GridOps<T>* ops = grid_ops<T>(c->n);
   const double* fo = c->d_fo + size_t(itau) * c->no;
   const double* fv = c->d_fv + size_t(itau) * c->nv;
   const long lda = 2L * c->nh * c->no;
@@ -547,24 +595,24 @@ ltmp2_status run_exchange(ltmp2_ctx* c, int itau, int g_first, int g_count) {
     const int M = 2 * gb * c->no;
     // P = C Psi_v in the real basis:  C_ja = fo_j fv_a n_aj(G')
     {
-    StageTimer tm(c, 3);
-    hipLaunchKernelGGL(k_gemm_kmajor, dim3((c->npw + 63) / 64, (M + 63) / 64), dim3(256), 0,
-                       c->stream, c->d_nd + 2L * g0 * c->no, lda, c->d_bpw, (long)c->npw, c->d_P,
-                       (long)c->npw, M, c->npw, c->nv, fv, fo, 2, c->no);
+      StageTimer tm(c, 3);
+      s = launch_gemm_kmajor<MODE>(static_cast<const T*>(c->d_nd) + 2L * g0 * c->no, lda,
+                                   c->d_bpw, (long)c->npw, c->d_P, (long)c->npw, M, c->npw, c->nv,
+                                   fv, fo, 2, c->no, c->stream);
     }
-    if ((s = check_launch(c, "k_gemm_kmajor(W)"))) return s;
+    if (s) return fail(c, s, "transformed-state GEMM launch failed");
     {
-    StageTimer tm(c, 4);
-    s = launch_wstates(c->n, c->d_P, c->npw, c->d_wq, c->d_wsgn, c->sc, gb * c->no,
-                            1.0 / std::sqrt(c->omega), reinterpret_cast<cplx<double>*>(c->d_w),
-                            c->nrp, c->stream);
+      StageTimer tm(c, 4);
+      s = ops->wstates(static_cast<const T*>(c->d_P), c->npw, c->d_wq, c->d_wsgn, c->sc, gb * c->no,
+                       1.0 / std::sqrt(c->omega), static_cast<cplx<T>*>(c->d_w), c->nrp,
+                       c->stream);
     }
     if (s) return fail(c, s, "transformed-state launch failed");
     {
-    StageTimer tm(c, 5);
-    s = launch_pair(c->n, c->d_psi, c->nrp, reinterpret_cast<const cplx<double>*>(c->d_w),
-                         c->no, c->d_pairs, c->npairs, gb, c->d_gdesc, c->ng, c->d_v, c->kmax_aux,
-                         c->dV * c->dV, c->d_xpart + size_t(g0) * c->npairs, c->stream);
+      StageTimer tm(c, 5);
+      s = ops->pair(static_cast<const T*>(c->d_psi), c->nrp, static_cast<const cplx<T>*>(c->d_w),
+                    c->no, c->d_pairs, c->npairs, gb, c->d_gdesc, c->ng, c->d_v, c->kmax_aux,
+                    c->dV * c->dV, c->d_xpart + size_t(g0) * c->npairs, c->stream);
     }
     if (s) return fail(c, s, "pair transform launch failed");
   }
@@ -572,6 +620,37 @@ ltmp2_status run_exchange(ltmp2_ctx* c, int itau, int g_first, int g_count) {
   hipLaunchKernelGGL(k_reduce_exchange, dim3(1), dim3(256), 0, c->stream, c->d_xpart, g_first,
                      g_count, c->npairs, c->d_v, c->d_scal + 2 * itau + 1);
   return check_launch(c, "k_reduce_exchange");
+}
+
+ltmp2_status run_exchange(ltmp2_ctx* c, int itau, int g_first, int g_count) {
+  if (c->prm.prec == LTMP2_FP64) return run_exchange_t<double, kF64>(c, itau, g_first, g_count);
+  return run_exchange_t<float, kF32>(c, itau, g_first, g_count);
+}
+
+// G_occ / G_vir rows into double buffers (float contexts go through chi as scratch)
+template <class T, int MODE>
+ltmp2_status green_t(ltmp2_ctx* c, int itau, int row0, int nrows, double* gocc, double* gvir) {
+  const double* fo = c->d_fo + size_t(itau) * c->no;
+  const double* fv = c->d_fv + size_t(itau) * c->nv;
+  const T* psi = static_cast<const T*>(c->d_psi);
+  for (int which = 0; which < 2; ++which) {
+    double* out = which ? gvir : gocc;
+    if (!out) continue;
+    const T* base = psi + (which ? size_t(c->no) * c->nrp : 0);
+    const int K = which ? c->nv : c->no;
+    void* dst = (sizeof(T) == sizeof(double)) ? static_cast<void*>(out) : c->d_chi;
+    ltmp2_status s = launch_gemm_kmajor<MODE>(base + row0, c->nrp, base, c->nrp, dst, (long)c->nr,
+                                              nrows, c->nr, K, which ? fv : fo, nullptr, 1, 1,
+                                              c->stream);
+    if (s) return fail(c, s, "Green's-function GEMM launch failed");
+    if (sizeof(T) != sizeof(double)) {
+      const long cnt = long(nrows) * c->nr;
+      hipLaunchKernelGGL(k_widen, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, c->stream,
+                         static_cast<const float*>(c->d_chi), out, cnt);
+      if ((s = check_launch(c, "k_widen"))) return s;
+    }
+  }
+  return LTMP2_OK;
 }
 
 }  // namespace
@@ -605,22 +684,12 @@ extern "C" ltmp2_status ltmp2_green(ltmp2_ctx* c, int itau, int row0, int nrows,
   if (row0 < 0 || nrows < 0 || row0 + nrows > c->nr)
     return fail(c, LTMP2_EINVAL, "row range outside [0, n_r)");
   if (nrows == 0) return LTMP2_OK;
-  const double* fo = c->d_fo + size_t(itau) * c->no;
-  const double* fv = c->d_fv + size_t(itau) * c->nv;
-  if (gocc) {
-    hipLaunchKernelGGL(k_gemm_kmajor, dim3((c->nr + 63) / 64, (nrows + 63) / 64), dim3(256), 0,
-                       c->stream, c->d_psi + row0, c->nrp, c->d_psi, c->nrp,
-                       reinterpret_cast<double*>(gocc), (long)c->nr, nrows, c->nr, c->no, fo,
-                       (const double*)nullptr, 1, 1);
-    if ((s = check_launch(c, "k_gemm_kmajor(G_occ)"))) return s;
-  }
-  if (gvir) {
-    const double* pv = c->d_psi + size_t(c->no) * c->nrp;
-    hipLaunchKernelGGL(k_gemm_kmajor, dim3((c->nr + 63) / 64, (nrows + 63) / 64), dim3(256), 0,
-                       c->stream, pv + row0, c->nrp, pv, c->nrp, reinterpret_cast<double*>(gvir),
-                       (long)c->nr, nrows, c->nr, c->nv, fv, (const double*)nullptr, 1, 1);
-    if ((s = check_launch(c, "k_gemm_kmajor(G_vir)"))) return s;
-  }
+  s = (c->prm.prec == LTMP2_FP64)
+          ? green_t<double, kF64>(c, itau, row0, nrows, static_cast<double*>(gocc),
+                                  static_cast<double*>(gvir))
+          : green_t<float, kF32>(c, itau, row0, nrows, static_cast<double*>(gocc),
+                                 static_cast<double*>(gvir));
+  if (s) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LTMP2_OK;
 }

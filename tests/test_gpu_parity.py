@@ -148,3 +148,39 @@ def test_small_cells(torch_cuda, seed, L, ecut, eaux, no, nt):
     assert abs(ex - ref["e_x_lt"]) <= 1e-9 * abs(ref["e_x_lt"])
     if no == 1:
         assert abs(ex + 0.5 * ed) <= 1e-9 * abs(ed)
+
+
+@pytest.mark.parametrize("prec,name", [(1, "fp32"), (2, "bf16x3")])
+def test_c1_energy_mixed(c1_case, prec, name):
+    # grown precision forms: FP32 storage / transforms / GEMMs (bf16x3: the
+    # Green's-function GEMMs on split-BF16 MFMA), FP64 accumulation of the
+    # traces and Laplace sums; bar: N_occ uHa per cell against the FP64 oracle
+    m, e, c, P, tau, w, ref = c1_case
+    _say("C1 energy", name)
+    with _ctx(C1, m, e, c, tau=tau, w=w, prec=prec) as ctx:
+        ed, ex, pt, qe = ctx.energy()
+    dd, dx = ed - ref["e_d_lt"], ex - ref["e_x_lt"]
+    print(f"[{name}] dE_d={dd:.3e} dE_x={dx:.3e} per-tau max "
+          f"{np.abs(pt[:, 0] - ref['per_tau_d']).max():.3e} "
+          f"{np.abs(pt[:, 1] - ref['per_tau_x']).max():.3e}", flush=True)
+    tol = C1.n_occ * 1e-6
+    assert abs(dd) < tol and abs(dx) < tol
+
+
+def test_c1_green_rows_fp32(c1_case, torch_cuda):
+    torch = torch_cuda
+    m, e, c, P, tau, w, ref = c1_case
+    n = C1.n
+    nr = n ** 3
+    perm = _lib_to_nat(n)
+    Go, Gv = P.green(tau[1])
+    _say("C1 green rows fp32")
+    with _ctx(C1, m, e, c, tau=tau, w=w, prec=1) as ctx:
+        go = torch.zeros((100, nr), dtype=torch.float64, device="cuda")
+        gv = torch.zeros((100, nr), dtype=torch.float64, device="cuda")
+        ctx.green(1, 300, 100, go, gv)
+    rows = perm[300:400]
+    ro = Go[rows][:, perm].real
+    rv = Gv[rows][:, perm].real
+    assert np.abs(go.cpu().numpy() - ro).max() < 2e-5 * np.abs(ro).max()
+    assert np.abs(gv.cpu().numpy() - rv).max() < 2e-5 * np.abs(rv).max()
