@@ -25,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12      # FP64 vector and matrix, FLOP/s
+PEAK_FP32 = 157.3e12     # FP32 vector and matrix, FLOP/s
+PEAK_BF16 = 2.5e15       # BF16 dense matrix, FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
 
 
@@ -94,6 +96,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -112,8 +115,9 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     t = time.time()
+    prec = {"fp64": 0, "fp32": 1, "bf16x3": 2}[args.prec]
     ctx = Context(spec.L, spec.n, spec.ecut, spec.eaux, m, e, c, spec.n_occ, spec.n_tau,
-                  stream=stream.cuda_stream)
+                  stream=stream.cuda_stream, prec=prec)
     torch.cuda.synchronize()
     info = ctx.info
     log(f"setup {time.time() - t:.1f}s: n_g={info.n_g} n_vir={info.n_vir} "
@@ -142,9 +146,16 @@ def main():
     if flops is not None:
         per_launch = flops * args.steps / max(launches, 1)
         ach = per_launch / per_launch_s
-        roof = {"bound": "alu" if dom == "pair" else "mfma", "achieved": ach / 1e12,
-                "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
-                "traffic": None}
+        if dom == "pair" or dom == "w_synth":
+            peak = PEAK_FP64 if args.prec == "fp64" else PEAK_FP32
+            bound = "alu"
+        else:
+            peak = {"fp64": PEAK_FP64, "fp32": PEAK_FP32, "bf16x3": PEAK_BF16}[args.prec]
+            if dom == "w_gemm" and args.prec == "bf16x3":
+                peak = PEAK_FP32
+            bound = "mfma"
+        roof = {"bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None}
     else:
         per_launch = byts * args.steps / max(launches, 1)
         ach = per_launch / per_launch_s
@@ -160,13 +171,14 @@ def main():
         cpu = cpu_baseline(spec, m, e, c)
     out = {"metric": "LTMP2 energies/sec", "value": args.steps / dt, "unit": "energies/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}[args.prec],
            "data": "synthetic",
            "config": {"workload": f"gamma-only LTMP2 cell L={spec.L} bohr, {spec.n}^3 grid, "
                                   f"E_cut={spec.ecut} Ha (n_pw={info.n_pw}), "
                                   f"E_aux={spec.eaux} Ha (n_g={info.n_g}), "
                                   f"n_occ={spec.n_occ}, n_tau={spec.n_tau}, seed={spec.seed}",
-                      "precision": "fp64", "quadrature": "plain minimax"},
+                      "precision": args.prec, "quadrature": "plain minimax"},
            "energy": {"e_direct": ed, "e_exchange": ex, "quad_delta": qe},
            "stage_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
            "roofline": roof, "cpu_baseline": cpu}

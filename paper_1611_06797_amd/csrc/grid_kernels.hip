@@ -112,9 +112,12 @@ ltmp2_status chi_cols(const cplx<T>* chihat, long ld, const int* gdesc, int ng, 
 template <class T>
 ltmp2_status wstates(const T* P, int npw, const int* wq, const signed char* wsgn, SphereCols sc,
                      int nitems, double scale, cplx<T>* w, long ld, hipStream_t st) {
-  const int nk = 2 * sc.kmax + 1, sx = choose_sx<T>(nk);
-  return launch(k_wstates<T, N>, dim3(nitems), slab_lds_bytes<T>(N, nk, sx), st, P, npw, wq, wsgn,
-                sc, sx, scale, w, ld);
+  const int nk = 2 * sc.kmax + 1;
+  const size_t extra = sizeof(cplx<T>) * size_t(npw);
+  int sx = std::min(N, 8);
+  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) + extra > kLdsCap) --sx;
+  return launch(k_wstates<T, N>, dim3(nitems), slab_lds_bytes<T>(N, nk, sx) + extra, st, P, npw,
+                wq, wsgn, sc, sx, scale, w, ld);
 }
 
 template <class T>
@@ -125,8 +128,10 @@ struct PairF {
                            int npairs, int gb, const int* gdesc, int ng, const double* v, int kmax,
                            double dV2, double* xpart, hipStream_t st) {
       const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
-      return launch(k_pair<T, N, OPT>, dim3(npairs, gb), slab_lds_bytes<T>(N, nk, sx), st, psi, ld,
-                    w, no, pairs, npairs, gdesc, ng, v, kmax, sx, dV2, xpart);
+      const long total = long(npairs) * gb;
+      const unsigned nblk = unsigned((total + 7) / 8 * 8);
+      return launch(k_pair<T, N, OPT>, dim3(nblk), slab_lds_bytes<T>(N, nk, sx), st, psi, ld, w,
+                    no, pairs, npairs, gb, gdesc, ng, v, kmax, sx, dV2, xpart);
     }
   };
 };

@@ -176,6 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict
 // with W_j(G) rebuilt from the real-basis product P = C Psi_v:
 //   P[(g, j, 0)][q] = sum_a Re C_ja B[a][q],  P[(g, j, 1)][q] = sum_a Im C_ja B[a][q],
 // where B[a][q] holds Re c_a(0), Re c_a(G_k), Im c_a(G_k) for the half sphere.
+// W_j(G) is rebuilt once per item into shared memory (after the slab buffers).
 // Entry e of the sphere (column order) uses wq[e] = q_re | (q_im + 1) << 16
 // and the sign s = +1 for G_k, -1 for -G_k (c_a(-G) = conj c_a(G)):
 //   W(G) = (P_re[q_re] - s P_im[q_im]) + i (P_im[q_re] + s P_re[q_im]).
@@ -195,7 +196,9 @@ __global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, i
   const T* pre = P + (2 * item) * long(npw);
   const T* pim = pre + npw;
   cplx<T>* out = w + item * ld;
-  auto cf = [&](int, int e) {
+  // W_j(G) for the whole sphere, staged once in shared memory
+  cplx<T>* Wl = L.tw + N;
+  for (int e = threadIdx.x; e < npw; e += kThreads) {
     const int q = wq[e];
     const int qr = q & 0xffff, qi = (q >> 16) - 1;
     const T s = T(wsgn[e]);
@@ -204,8 +207,10 @@ __global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, i
       re -= s * pim[qi];
       im += s * pre[qi];
     }
-    return cplx<T>{T(re), T(im)};
-  };
+    Wl[e] = {re, im};
+  }
+  __syncthreads();
+  auto cf = [&](int, int e) { return Wl[e]; };
   auto st = [&](int, int x, int y, int z, cplx<T> v) {
     out[(x * N + z) * N + y] = {T(scale) * v.x, T(scale) * v.y};
   };
@@ -223,16 +228,24 @@ template <class T, int N, int OPT>
 __global__ __launch_bounds__(kThreads) void k_pair(const T* __restrict__ psi, long ld,
                                                    const cplx<T>* __restrict__ w, int nocc,
                                                    const int* __restrict__ pairs, int npairs,
-                                                   const int* __restrict__ gdesc_all, int ng,
-                                                   const double* __restrict__ v, int kmax, int sx,
-                                                   double dV2, double* __restrict__ xpart) {
+                                                   int gb, const int* __restrict__ gdesc_all,
+                                                   int ng, const double* __restrict__ v, int kmax,
+                                                   int sx, double dV2,
+                                                   double* __restrict__ xpart) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[kThreads / 64];
   const int nk = 2 * kmax + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, -1>(L.tw, N);
-  const int p = blockIdx.x;
-  const int gl = blockIdx.y;
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of the (G', pair) list, pairs in i-major order, so the
+  // workgroups resident on one XCD share (G', i) and psi_i, w_i stay in its L2.
+  const long total = long(npairs) * gb;
+  const long per_xcd = (total + 7) / 8;
+  const long t = long(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= total) return;
+  const int gl = int(t / npairs);
+  const int p = int(t - long(gl) * npairs);
   const int i = pairs[p] & 0xffff, j = pairs[p] >> 16;
   const T* pi = psi + long(i) * ld;
   const T* pj = psi + long(j) * ld;

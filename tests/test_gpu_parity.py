@@ -184,3 +184,52 @@ def test_c1_green_rows_fp32(c1_case, torch_cuda):
     rv = Gv[rows][:, perm].real
     assert np.abs(go.cpu().numpy() - ro).max() < 2e-5 * np.abs(ro).max()
     assert np.abs(gv.cpu().numpy() - rv).max() < 2e-5 * np.abs(rv).max()
+
+
+@pytest.fixture(scope="module")
+def c2_cell(torch_cuda):
+    from synthetic import C2
+    m, e, c = make_cell(C2)
+    return C2, m, e, c
+
+
+def test_c2_occupied_subset_vs_oracle(c2_cell):
+    # full 32^3 grid, all 3895 virtuals, occupied subset I = {58, 61, 62, 63}:
+    # the energy restricted to i, j in I against the oracle (same tau, w)
+    spec, m, e, c = c2_cell
+    occ = np.array([58, 61, 62, 63])
+    _say("C2 occupied subset", occ.tolist())
+    from oracle.mp2 import Problem
+    from oracle.quadrature import minimax_laplace
+    P = Problem(spec.L, spec.n, spec.eaux, m, e, c, spec.n_occ, occ=occ)
+    tau, w, _ = minimax_laplace(*P.x_range(), spec.n_tau)
+    ref = P.energies(tau, w)
+    sel = np.concatenate([occ, np.arange(spec.n_occ, len(e))])
+    sub = CellSpec(L=spec.L, n=spec.n, ecut=spec.ecut, eaux=spec.eaux, n_occ=len(occ),
+                   n_tau=spec.n_tau, seed=spec.seed)
+    for prec in (0, 1, 2):
+        with _ctx(sub, m, e[sel], c[sel], tau=tau, w=w, prec=prec) as ctx:
+            ed, ex, pt, qe = ctx.energy()
+        dd, dx = ed - ref["e_d_lt"], ex - ref["e_x_lt"]
+        print(f"[c2-subset prec={prec}] E_d={ed:.10f} dE_d={dd:.3e} E_x={ex:.10f} dE_x={dx:.3e}",
+              flush=True)
+        assert abs(dd) < len(occ) * 1e-6 and abs(dx) < len(occ) * 1e-6
+        if prec == 0:
+            assert abs(dd) <= 1e-9 * abs(ref["e_d_lt"]) and abs(dx) <= 1e-9 * abs(ref["e_x_lt"])
+
+
+def test_c2_full_precision_forms(c2_cell):
+    # full throughput workload (64 occupied): FP32 and BF16x3 against FP64 GPU
+    # within N_occ uHa; E_d(tau) <= 0 and E_x(tau) >= 0 at every point
+    spec, m, e, c = c2_cell
+    res = {}
+    for prec in (0, 1, 2):
+        _say("C2 full, prec", prec)
+        with _ctx(spec, m, e, c, prec=prec) as ctx:
+            res[prec] = ctx.energy()
+    ed0, ex0, pt0, _ = res[0]
+    assert np.all(pt0[:, 0] < 0) and np.all(pt0[:, 1] > 0)
+    for prec in (1, 2):
+        ed, ex, pt, _ = res[prec]
+        print(f"[c2 prec={prec}] dE_d={ed - ed0:.3e} dE_x={ex - ex0:.3e}", flush=True)
+        assert abs(ed - ed0) < spec.n_occ * 1e-6 and abs(ex - ex0) < spec.n_occ * 1e-6
