@@ -95,6 +95,9 @@ typedef struct {
   double x_min, x_max;   /* bounds of -D = e_a + e_b - e_i - e_j          */
   double quad_delta;     /* certified max relative quadrature error       */
   size_t device_bytes;   /* device memory held by the context             */
+  int quad_flags;        /* LTMP2_QUAD_LEARNED only: bit 0 the polished MLP
+                            proposal was certified, bit 1 the plain fit was
+                            used instead, bit 2 the weight file was unusable */
 } ltmp2_info;
 
 /*
@@ -106,7 +109,9 @@ typedef struct {
  *   eps    [n_states]        orbital energies, ascending
  *   coeff  [n_states][n_pw][2]  state-major coefficients c_p(G), (re, im)
  *   tau, w [n_tau]           quadrature (only with LTMP2_QUAD_GIVEN, else NULL)
- *   mlp_weights              path of a weight file (LTMP2_QUAD_LEARNED), else NULL
+ *   mlp_weights              path of a weight file (LTMP2_QUAD_LEARNED), else NULL;
+ *                            the proposal is polished by 3 Remez passes and
+ *                            certified to 1e-6, else the plain fit is used
  *   hip_stream               hipStream_t to run on (NULL: default stream)
  * On success *out receives a context; on failure *out is NULL.
  */
@@ -192,6 +197,62 @@ ltmp2_status ltmp2_quadrature(double x_min, double x_max, int n_tau, double* tau
  */
 ltmp2_status ltmp2_set_timing(ltmp2_ctx* ctx, int on);
 ltmp2_status ltmp2_get_timing(ltmp2_ctx* ctx, int stage, double* ms, long* launches);
+
+/*
+ * Learned Laplace quadrature (grown form of the quadrature step).  A small
+ * network 3 -> 64 (tanh) -> 64 (tanh) -> 24 (FP32, LTMP2_MLP_NPARAM floats:
+ * W1[64][3] b1[64] W2[64][64] b2[64] W3[24][64] b3[24]) maps the features
+ * (log x_min, log R / log 1e4, n_tau / 12), R = x_max / x_min, to the
+ * logarithms of the unit-interval exponents (outputs 0..11) and weights
+ * (outputs 12..23) of the n_tau-point minimax fit.  It is trained on the GPU
+ * by the library's own forward / backward / Adam kernels on fits that the
+ * plain method generates.  Weight files: 8 bytes "LTMP2MLP", uint32 version
+ * (1), uint32 count (LTMP2_MLP_NPARAM), then the floats, little endian.
+ */
+#define LTMP2_MLP_NPARAM 5976
+
+/* Seeded Glorot-uniform initial parameters (host). */
+ltmp2_status ltmp2_mlp_init(uint64_t seed, float* params);
+
+/* Plain minimax fits for ascending ratios R[0..count) in one continuation
+ * sweep (host): alpha, beta [count][n_tau] on [1, max(R, R_floor)], delta
+ * [count] (may be NULL). */
+ltmp2_status ltmp2_quadrature_table(int n_tau, int count, const double* R, double* alpha,
+                                    double* beta, double* delta);
+
+/* Seeded training set (host): count samples with x_min log-uniform in
+ * [dmin_lo, dmin_hi], R log-uniform in [ratio_lo, ratio_hi], n_tau drawn from
+ * n_taus[0..n_choices) (each in 1..12), random numbers from splitmix64(seed);
+ * X [count][3] features, Y [count][24] targets, M [count][24] mask,
+ * xrange [count][2] (x_min, x_max) or NULL. */
+ltmp2_status ltmp2_mlp_dataset(int count, uint64_t seed, double dmin_lo, double dmin_hi,
+                               double ratio_lo, double ratio_hi, const int* n_taus, int n_choices,
+                               float* X, float* Y, float* M, double* xrange);
+
+/* Network outputs for n inputs (host arrays; computed on the GPU). */
+ltmp2_status ltmp2_mlp_forward(const float* params, const float* X, int n, float* Y,
+                               void* hip_stream);
+
+/* Gradient of the masked mean squared error (host arrays; GPU kernels):
+ * grad [LTMP2_MLP_NPARAM], *loss = sum M (out - Y)^2 / sum M. */
+ltmp2_status ltmp2_mlp_grad(const float* params, const float* X, const float* Y, const float* M,
+                            int n, float* grad, float* loss, void* hip_stream);
+
+/* Adam training on the GPU (cosine learning-rate decay, seeded shuffles);
+ * params is updated in place; loss_hist [epochs] may be NULL. */
+ltmp2_status ltmp2_mlp_train(float* params, const float* X, const float* Y, const float* M, int n,
+                             int epochs, int batch, float lr, uint64_t seed, float* loss_hist,
+                             void* hip_stream);
+
+/* MLP proposal for [x_min, x_max], polish_steps Remez passes, certification
+ * (2 n_tau + 1 alternating extrema equal to cert_tol relative), else the
+ * plain fit.  flags: bit 0 certified, bit 1 fell back to the plain fit. */
+ltmp2_status ltmp2_learned_quadrature(const float* params, double x_min, double x_max, int n_tau,
+                                      int polish_steps, double cert_tol, double* tau, double* w,
+                                      double* delta, int* flags, void* hip_stream);
+
+/* Message of the last failed MLP / table call on this thread. */
+const char* ltmp2_mlp_last_error(void);
 
 /* Release a context and all of its device memory (NULL is ignored). */
 void ltmp2_destroy(ltmp2_ctx* ctx);

@@ -45,7 +45,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     units = [("registry.hip", "registry.o", []),
              ("ltmp2.hip", "ltmp2.o", []),
-             ("quadrature.cpp", "quadrature.o", ["-x", "hip"])]
+             ("quadrature.cpp", "quadrature.o", ["-x", "hip"]),
+             ("mlp.hip", "mlp.o", [])]
     units += [("grid_kernels.hip", f"grid_{n}.o", [f"-DLTMP2_N={n}"]) for n in GRIDS]
     cmds = []
     for src, obj, extra in units:

@@ -39,6 +39,8 @@ struct ltmp2_ctx {
   long nrp = 0;  // padded row stride of grid arrays (multiple of 64)
   int kmax_aux = 0, kmax_orb = 0, gblock = 0;
   double omega = 0, dV = 0, mu = 0, xmin = 0, xmax = 0, quad_delta = 0;
+  int quad_flags = 0;
+  std::string mlp_path;
   std::vector<double> eps, tau, w;
   std::vector<int> aux;  // [ng][3], H first then -H
 
@@ -169,8 +171,8 @@ ltmp2_status validate(const ltmp2_params* p, const int32_t* miller, const double
   if (p->n_tau < 1 || p->n_tau > 16) return fail(nullptr, LTMP2_EINVAL, "n_tau must be in [1, 16]");
   if (p->prec < 0 || p->prec > 2) return fail(nullptr, LTMP2_EINVAL, "unknown precision");
   if (p->quad_mode < 0 || p->quad_mode > 2) return fail(nullptr, LTMP2_EINVAL, "unknown quad_mode");
-  if (p->quad_mode == LTMP2_QUAD_LEARNED)
-    return fail(nullptr, LTMP2_EINVAL, "learned quadrature is not available in this build");
+  if (p->quad_mode == LTMP2_QUAD_LEARNED && p->n_tau > 12)
+    return fail(nullptr, LTMP2_EINVAL, "learned quadrature covers n_tau <= 12");
   if (!miller || !eps || !coeff) return fail(nullptr, LTMP2_EINVAL, "NULL input array");
   if (p->quad_mode == LTMP2_QUAD_GIVEN) {
     if (!tau || !w) return fail(nullptr, LTMP2_EINVAL, "tau and w required with LTMP2_QUAD_GIVEN");
@@ -220,6 +222,27 @@ ltmp2_status validate(const ltmp2_params* p, const int32_t* miller, const double
                   "orbital " + std::to_string(s) + " is not real on the grid (c(-G) != conj c(G))");
   }
   return LTMP2_OK;
+}
+
+// Weight file: "LTMP2MLP", uint32 version 1, uint32 count, count floats.
+bool read_mlp_weights(const std::string& path, std::vector<float>& out) {
+  if (path.empty()) return false;
+  FILE* f = std::fopen(path.c_str(), "rb");
+  if (!f) return false;
+  char magic[8];
+  uint32_t ver = 0, cnt = 0;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "LTMP2MLP", 8) == 0 &&
+            std::fread(&ver, 4, 1, f) == 1 && std::fread(&cnt, 4, 1, f) == 1 && ver == 1 &&
+            cnt == LTMP2_MLP_NPARAM;
+  if (ok) {
+    out.resize(cnt);
+    ok = std::fread(out.data(), sizeof(float), cnt, f) == cnt;
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;
+    for (float v : out) ok = ok && std::isfinite(v);
+  }
+  std::fclose(f);
+  return ok;
 }
 
 // Launch helpers --------------------------------------------------------------
@@ -460,6 +483,19 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
       d = std::max(d, std::fabs(x * s - 1.0));
     }
     c->quad_delta = d;
+  } else if (P.quad_mode == LTMP2_QUAD_LEARNED) {
+    std::vector<float> prm;
+    if (!read_mlp_weights(c->mlp_path, prm)) {
+      c->quad_flags = 4 | 2;
+      const int r = minimax_quadrature(c->xmin, c->xmax, c->ntau, c->tau.data(), c->w.data(),
+                                       &c->quad_delta);
+      if (r != 0) return fail(nullptr, LTMP2_ENUMERIC, "minimax quadrature did not converge");
+    } else {
+      ltmp2_status q = ltmp2_learned_quadrature(prm.data(), c->xmin, c->xmax, c->ntau, 3, 1e-6,
+                                                c->tau.data(), c->w.data(), &c->quad_delta,
+                                                &c->quad_flags, c->stream);
+      if (q) return fail(nullptr, q, std::string("learned quadrature: ") + ltmp2_mlp_last_error());
+    }
   } else {
     const int r = minimax_quadrature(c->xmin, c->xmax, c->ntau, c->tau.data(), c->w.data(),
                                      &c->quad_delta);
@@ -659,13 +695,13 @@ extern "C" ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller
                                     const double* eps, const double* coeff, const double* tau,
                                     const double* w, const char* mlp_weights, void* hip_stream,
                                     ltmp2_ctx** out) {
-  (void)mlp_weights;
   if (!out) return fail(nullptr, LTMP2_EINVAL, "out is NULL");
   *out = nullptr;
   ltmp2_status s = validate(p, miller, eps, coeff, tau, w);
   if (s) return s;
   ltmp2_ctx* c = new ltmp2_ctx();
   c->prm = *p;
+  if (mlp_weights) c->mlp_path = mlp_weights;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   s = setup_impl(c, miller, eps, coeff, tau, w);
   if (s) {
@@ -772,6 +808,7 @@ extern "C" ltmp2_status ltmp2_get_info(const ltmp2_ctx* c, ltmp2_info* info) {
   info->x_max = c->xmax;
   info->quad_delta = c->quad_delta;
   info->device_bytes = c->bytes;
+  info->quad_flags = c->quad_flags;
   return LTMP2_OK;
 }
 

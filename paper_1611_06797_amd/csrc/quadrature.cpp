@@ -103,8 +103,11 @@ struct Ref {
   double emax = 0.0;
 };
 
+thread_local int g_ngrid = 20000;  // bracketing grid of the extremum search
+
 // Alternating extrema of e on [1, R].
-Ref alternation(int N, double R, const Vec& p, const Vec& q, int ngrid = 20000) {
+Ref alternation(int N, double R, const Vec& p, const Vec& q) {
+  const int ngrid = g_ngrid;
   const double T = std::log(R);
   const double h = T / (ngrid - 1);
   Vec e(ngrid);
@@ -464,6 +467,69 @@ int remez_polish(double x_min, double x_max, int n, int steps, double cert_tol, 
   }
   if (delta) *delta = r.emax;
   if (certified) *certified = cert;
+  return 0;
+}
+
+int quadrature_table(int n, int count, const double* R, double* alpha, double* beta,
+                     double* delta) {
+  if (n < 1 || n > 16 || count < 0) return 1;
+  for (int k = 1; k < count; ++k)
+    if (!(R[k] >= R[k - 1])) return 1;
+  if (count == 0) return 0;
+  if (!(R[0] > 1.0)) return 1;
+  const int saved = g_ngrid;
+  g_ngrid = 4000;
+  double R0;
+  State s;
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_start.find(n);
+    if (it != g_start.end()) {
+      R0 = it->second.first;
+      s = it->second.second;
+      have = true;
+    }
+  }
+  if (!have) {
+    g_ngrid = 20000;
+    if (!start_fit(n, R0, s)) {
+      g_ngrid = saved;
+      return 2;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_start[n] = {R0, s};
+  }
+  g_ngrid = 4000;
+  const double fl = quad_r_floor(n);
+  double cur = R0;
+  for (int k = 0; k < count; ++k) {
+    const double target = std::max(R[k], fl);
+    if (std::fabs(std::log(target / cur)) > 1e-13) {
+      State keep = s;
+      if (!walk(n, cur, s, target)) {
+        // near the double-precision floor the coarse bracketing grid can
+        // miss an extremum: repeat the step with the fine grid
+        s = keep;
+        g_ngrid = 20000;
+        const bool ok = walk(n, cur, s, target);
+        g_ngrid = 4000;
+        if (!ok) {
+          g_ngrid = saved;
+          return 2;
+        }
+      }
+      cur = target;
+    }
+    Vec p = s.p, q = s.q;
+    sort_pq(p, q);
+    for (int t = 0; t < n; ++t) {
+      alpha[size_t(k) * n + t] = std::exp(p[t]);
+      beta[size_t(k) * n + t] = std::exp(q[t]);
+    }
+    if (delta) delta[k] = s.delta;
+  }
+  g_ngrid = saved;
   return 0;
 }
 

@@ -14,4 +14,9 @@ int minimax_quadrature(double x_min, double x_max, int n, double* tau, double* w
 int remez_polish(double x_min, double x_max, int n, int steps, double cert_tol, double* tau,
                  double* w, double* delta, int* certified);
 
+// Minimax fits on [1, max(R[k], R_floor)] for ascending R[0..count) by one
+// continuation sweep: alpha, beta [count][n] (unit interval), delta [count].
+int quadrature_table(int n, int count, const double* R, double* alpha, double* beta,
+                     double* delta);
+
 }  // namespace ltmp2

@@ -23,7 +23,10 @@ QUAD_PLAIN, QUAD_LEARNED, QUAD_GIVEN = 0, 1, 2
 EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
             "ltmp2_get_quadrature", "ltmp2_get_info", "ltmp2_aux_miller", "ltmp2_quadrature",
             "ltmp2_destroy", "ltmp2_last_error", "ltmp2_supported_grids", "ltmp2_set_timing",
-            "ltmp2_get_timing")
+            "ltmp2_get_timing", "ltmp2_mlp_init", "ltmp2_quadrature_table", "ltmp2_mlp_dataset",
+            "ltmp2_mlp_forward", "ltmp2_mlp_grad", "ltmp2_mlp_train", "ltmp2_learned_quadrature",
+            "ltmp2_mlp_last_error")
+MLP_NPARAM = 5976
 STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
 
 
@@ -39,7 +42,7 @@ class Info(C.Structure):
     _fields_ = [("n_r", C.c_int), ("n_g", C.c_int), ("n_h", C.c_int), ("n_pw", C.c_int),
                 ("n_occ", C.c_int), ("n_vir", C.c_int), ("n_tau", C.c_int),
                 ("x_min", C.c_double), ("x_max", C.c_double), ("quad_delta", C.c_double),
-                ("device_bytes", C.c_size_t)]
+                ("device_bytes", C.c_size_t), ("quad_flags", C.c_int)]
 
 
 class LTMP2Error(RuntimeError):
@@ -82,9 +85,24 @@ def load(path: str = LIB_PATH):
     lib.ltmp2_supported_grids.argtypes = [C.c_void_p, C.c_int]
     lib.ltmp2_set_timing.argtypes = [C.c_void_p, C.c_int]
     lib.ltmp2_get_timing.argtypes = [C.c_void_p, C.c_int, dp, C.POINTER(C.c_long)]
+    vp = C.c_void_p
+    lib.ltmp2_mlp_init.argtypes = [C.c_uint64, vp]
+    lib.ltmp2_quadrature_table.argtypes = [C.c_int, C.c_int, vp, vp, vp, vp]
+    lib.ltmp2_mlp_dataset.argtypes = [C.c_int, C.c_uint64, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, vp, C.c_int, vp, vp, vp, vp]
+    lib.ltmp2_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp]
+    lib.ltmp2_mlp_grad.argtypes = [vp, vp, vp, vp, C.c_int, vp, C.POINTER(C.c_float), vp]
+    lib.ltmp2_mlp_train.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_float,
+                                    C.c_uint64, vp, vp]
+    lib.ltmp2_learned_quadrature.argtypes = [vp, C.c_double, C.c_double, C.c_int, C.c_int,
+                                             C.c_double, vp, vp, dp, C.POINTER(C.c_int), vp]
+    lib.ltmp2_mlp_last_error.argtypes = []
+    lib.ltmp2_mlp_last_error.restype = C.c_char_p
     for name in ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
                  "ltmp2_get_quadrature", "ltmp2_get_info", "ltmp2_aux_miller",
-                 "ltmp2_quadrature", "ltmp2_set_timing", "ltmp2_get_timing"):
+                 "ltmp2_quadrature", "ltmp2_set_timing", "ltmp2_get_timing", "ltmp2_mlp_init",
+                 "ltmp2_quadrature_table", "ltmp2_mlp_dataset", "ltmp2_mlp_forward",
+                 "ltmp2_mlp_grad", "ltmp2_mlp_train", "ltmp2_learned_quadrature"):
         getattr(lib, name).restype = C.c_int
     lib.ltmp2_supported_grids.restype = C.c_int
     _lib = lib
@@ -117,6 +135,106 @@ def quadrature(x_min: float, x_max: float, n_tau: int):
     return tau, w, d.value
 
 
+def _mcheck(lib, st):
+    if st != 0:
+        raise LTMP2Error(st, lib.ltmp2_mlp_last_error().decode())
+
+
+def quadrature_table(n_tau, R):
+    """Minimax fits (alpha, beta [len(R), n_tau], delta) for ascending R (unit interval)."""
+    lib = load()
+    R = np.ascontiguousarray(R, np.float64)
+    a = np.zeros((len(R), n_tau))
+    b = np.zeros((len(R), n_tau))
+    d = np.zeros(len(R))
+    _mcheck(lib, lib.ltmp2_quadrature_table(n_tau, len(R), _ptr(R), _ptr(a), _ptr(b), _ptr(d)))
+    return a, b, d
+
+
+def mlp_init(seed):
+    lib = load()
+    p = np.zeros(MLP_NPARAM, np.float32)
+    _mcheck(lib, lib.ltmp2_mlp_init(seed, _ptr(p)))
+    return p
+
+
+def mlp_dataset(count, seed, dmin=(0.05, 1.0), ratio=(10.0, 1e4), n_taus=(6, 8, 10, 12)):
+    """Seeded training set (X [count, 3], Y [count, 24], M [count, 24], xrange [count, 2])."""
+    lib = load()
+    X = np.zeros((count, 3), np.float32)
+    Y = np.zeros((count, 24), np.float32)
+    M = np.zeros((count, 24), np.float32)
+    xr = np.zeros((count, 2))
+    nt = np.ascontiguousarray(n_taus, np.int32)
+    _mcheck(lib, lib.ltmp2_mlp_dataset(count, seed, dmin[0], dmin[1], ratio[0], ratio[1],
+                                       _ptr(nt), len(nt), _ptr(X), _ptr(Y), _ptr(M), _ptr(xr)))
+    return X, Y, M, xr
+
+
+def mlp_forward(params, X):
+    lib = load()
+    X = np.ascontiguousarray(X, np.float32)
+    out = np.zeros((X.shape[0], 24), np.float32)
+    _mcheck(lib, lib.ltmp2_mlp_forward(_ptr(np.ascontiguousarray(params, np.float32)), _ptr(X),
+                                       X.shape[0], _ptr(out), C.c_void_p(_current_stream())))
+    return out
+
+
+def mlp_grad(params, X, Y, M):
+    lib = load()
+    X, Y, M = (np.ascontiguousarray(a, np.float32) for a in (X, Y, M))
+    g = np.zeros(MLP_NPARAM, np.float32)
+    loss = C.c_float()
+    _mcheck(lib, lib.ltmp2_mlp_grad(_ptr(np.ascontiguousarray(params, np.float32)), _ptr(X),
+                                    _ptr(Y), _ptr(M), X.shape[0], _ptr(g), C.byref(loss),
+                                    C.c_void_p(_current_stream())))
+    return g, loss.value
+
+
+def mlp_train(params, X, Y, M, epochs, batch, lr, seed):
+    """Train in place on the GPU; returns the per-epoch loss."""
+    lib = load()
+    X, Y, M = (np.ascontiguousarray(a, np.float32) for a in (X, Y, M))
+    assert params.dtype == np.float32 and params.flags.c_contiguous
+    hist = np.zeros(epochs, np.float32)
+    _mcheck(lib, lib.ltmp2_mlp_train(_ptr(params), _ptr(X), _ptr(Y), _ptr(M), X.shape[0], epochs,
+                                     batch, lr, seed, _ptr(hist), C.c_void_p(_current_stream())))
+    return hist
+
+
+def learned_quadrature(params, x_min, x_max, n_tau, polish_steps=3, cert_tol=1e-6):
+    """(tau, w, delta, flags): MLP proposal + Remez polish, certified, else the plain fit."""
+    lib = load()
+    tau = np.zeros(n_tau)
+    w = np.zeros(n_tau)
+    d = C.c_double()
+    fl = C.c_int()
+    _mcheck(lib, lib.ltmp2_learned_quadrature(
+        _ptr(np.ascontiguousarray(params, np.float32)), x_min, x_max, n_tau, polish_steps,
+        cert_tol, _ptr(tau), _ptr(w), C.byref(d), C.byref(fl), C.c_void_p(_current_stream())))
+    return tau, w, d.value, fl.value
+
+
+def write_mlp_weights(path, params):
+    import struct
+    p = np.ascontiguousarray(params, np.float32)
+    assert p.size == MLP_NPARAM
+    with open(path, "wb") as f:
+        f.write(b"LTMP2MLP" + struct.pack("<II", 1, MLP_NPARAM))
+        f.write(p.astype("<f4").tobytes())
+
+
+def read_mlp_weights(path):
+    import struct
+    raw = open(path, "rb").read()
+    if raw[:8] != b"LTMP2MLP":
+        raise ValueError("not an LTMP2 MLP weight file")
+    ver, cnt = struct.unpack("<II", raw[8:16])
+    if ver != 1 or cnt != MLP_NPARAM or len(raw) != 16 + 4 * cnt:
+        raise ValueError("unsupported or truncated weight file")
+    return np.frombuffer(raw[16:], "<f4").astype(np.float32)
+
+
 class Context:
     """One prepared cell (ltmp2_setup ... ltmp2_destroy)."""
 
@@ -131,7 +249,8 @@ class Context:
             coeff = np.stack([coeff.real, coeff.imag], axis=-1)
         coeff = np.ascontiguousarray(coeff, np.float64)
         if quad_mode is None:
-            quad_mode = QUAD_GIVEN if tau is not None else QUAD_PLAIN
+            quad_mode = QUAD_GIVEN if tau is not None else (
+                QUAD_LEARNED if mlp_weights else QUAD_PLAIN)
         tau_a = None if tau is None else np.ascontiguousarray(tau, np.float64)
         w_a = None if w is None else np.ascontiguousarray(w, np.float64)
         p = Params(float(L), int(n_fft), float(ecut), float(eaux), int(miller.shape[0]),

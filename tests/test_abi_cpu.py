@@ -120,3 +120,38 @@ def test_workspace_cap_enomem(lib, cell):
 def test_last_error_for_null_context(lib):
     lib.load().ltmp2_destroy(None)          # NULL is ignored
     assert isinstance(lib.load().ltmp2_last_error(None), bytes)
+
+
+def test_quadrature_table_matches_oracle(lib):
+    from oracle.quadrature import minimax_unit
+    R = np.array([12.0, 40.0, 133.0, 900.0, 5000.0])
+    a, b, d = lib.quadrature_table(8, R)
+    for k, r in enumerate(R):
+        ao, bo, do = minimax_unit(8, r)
+        assert np.allclose(a[k], ao, rtol=1e-7) and np.allclose(b[k], bo, rtol=1e-7)
+        assert abs(d[k] - do) <= 1e-6 * do
+
+
+def test_mlp_dataset_targets_are_minimax_fits(lib):
+    from oracle.quadrature import minimax_unit
+    X, Y, M, xr = lib.mlp_dataset(300, 5, n_taus=(6, 8))
+    assert np.all(M.sum(1) == 2 * np.round(X[:, 2] * 12))
+    assert np.all((xr[:, 0] >= 0.05) & (xr[:, 0] <= 1.0))
+    R = xr[:, 1] / xr[:, 0]
+    assert np.all((R >= 10 - 1e-9) & (R <= 1e4 + 1e-6))
+    for k in (0, 17, 299):
+        n = int(round(X[k, 2] * 12))
+        a, b, d = minimax_unit(n, R[k])
+        assert np.allclose(Y[k, :n], np.log(a), atol=1e-6)
+        assert np.allclose(Y[k, 12:12 + n], np.log(b), atol=1e-6)
+    X2, Y2, M2, _ = lib.mlp_dataset(300, 5, n_taus=(6, 8))
+    assert np.array_equal(X, X2) and np.array_equal(Y, Y2)
+
+
+def test_mlp_init_and_weight_file(lib, tmp_path):
+    p = lib.mlp_init(11)
+    assert p.shape == (lib.MLP_NPARAM,) and np.all(np.isfinite(p))
+    assert np.array_equal(p, lib.mlp_init(11)) and not np.array_equal(p, lib.mlp_init(12))
+    f = tmp_path / "w.bin"
+    lib.write_mlp_weights(str(f), p)
+    assert np.array_equal(lib.read_mlp_weights(str(f)), p)
