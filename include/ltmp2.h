@@ -251,6 +251,12 @@ ltmp2_status ltmp2_learned_quadrature(const float* params, double x_min, double 
                                       int polish_steps, double cert_tol, double* tau, double* w,
                                       double* delta, int* flags, void* hip_stream);
 
+/* Host-only Remez polish of a proposal (tau, w updated in place): `steps`
+ * exchange passes on [x_min, x_max]; *certified = 1 if the 2 n_tau + 1
+ * alternating extrema agree to cert_tol relative. */
+ltmp2_status ltmp2_remez_polish(double x_min, double x_max, int n_tau, int steps, double cert_tol,
+                                double* tau, double* w, double* delta, int* certified);
+
 /* Message of the last failed MLP / table call on this thread. */
 const char* ltmp2_mlp_last_error(void);
 

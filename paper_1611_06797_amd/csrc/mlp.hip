@@ -466,4 +466,13 @@ extern "C" ltmp2_status ltmp2_learned_quadrature(const float* params, double x_m
   return LTMP2_OK;
 }
 
+extern "C" ltmp2_status ltmp2_remez_polish(double x_min, double x_max, int n_tau, int steps,
+                                           double cert_tol, double* tau, double* w, double* delta,
+                                           int* certified) {
+  if (!tau || !w) return mfail(LTMP2_EINVAL, "NULL array");
+  if (remez_polish(x_min, x_max, n_tau, steps, cert_tol, tau, w, delta, certified) != 0)
+    return mfail(LTMP2_EINVAL, "bad arguments");
+  return LTMP2_OK;
+}
+
 extern "C" const char* ltmp2_mlp_last_error(void) { return mlp_last_error(); }

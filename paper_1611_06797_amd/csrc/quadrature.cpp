@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "quadrature.h"
+#include "reference_table.h"
 
 namespace ltmp2 {
 namespace {
@@ -436,6 +437,38 @@ int remez_polish(double x_min, double x_max, int n, int steps, double cert_tol, 
     q[k] = std::log(w[k] * x_min);
   }
   sort_pq(p, q);
+  // A proposal whose error is far above the optimum shows too few
+  // alternations for the exchange to start.  Solve the equioscillation system
+  // first at a model reference: the normalised alternation points
+  // t_k = log y_k / log R of plain fits, tabulated for N <= 12 at four ratios
+  // and interpolated in log R (they depend only weakly on R); the solution
+  // alternates at those points by construction.
+  if (n <= 12) {
+    const double T = std::log(R);
+    const double* rr = kRefR[n - 1];
+    int i0 = 0;
+    while (i0 < 2 && R > rr[i0 + 1]) ++i0;
+    double u = (std::log(R) - std::log(rr[i0])) / (std::log(rr[i0 + 1]) - std::log(rr[i0]));
+    u = std::clamp(u, 0.0, 1.0);
+    Vec ref(2 * n + 1);
+    for (int k = 0; k <= 2 * n; ++k) {
+      const double t = (1.0 - u) * kRefT[n - 1][i0][k] + u * kRefT[n - 1][i0 + 1][k];
+      ref[k] = std::exp(t * T);
+    }
+    double mean = 0.0;
+    for (double y : ref) mean += std::fabs(err1(y, p, q));
+    mean /= ref.size();
+    Vec p2 = p, q2 = q;
+    if (newton_reference(n, ref, p2, q2, (err1(ref[0], p, q) < 0 ? -1.0 : 1.0) * mean)) {
+      sort_pq(p2, q2);
+      bool ok = true;
+      for (int k = 0; k < n; ++k) ok = ok && std::isfinite(p2[k]) && std::isfinite(q2[k]);
+      if (ok) {
+        p = p2;
+        q = q2;
+      }
+    }
+  }
   for (int it = 0; it < steps; ++it) {
     Ref r = alternation(n, R, p, q);
     if ((int)r.y.size() < 2 * n + 1) break;

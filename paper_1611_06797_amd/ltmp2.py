@@ -25,7 +25,7 @@ EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_
             "ltmp2_destroy", "ltmp2_last_error", "ltmp2_supported_grids", "ltmp2_set_timing",
             "ltmp2_get_timing", "ltmp2_mlp_init", "ltmp2_quadrature_table", "ltmp2_mlp_dataset",
             "ltmp2_mlp_forward", "ltmp2_mlp_grad", "ltmp2_mlp_train", "ltmp2_learned_quadrature",
-            "ltmp2_mlp_last_error")
+            "ltmp2_mlp_last_error", "ltmp2_remez_polish")
 MLP_NPARAM = 5976
 STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
 
@@ -96,6 +96,9 @@ def load(path: str = LIB_PATH):
                                     C.c_uint64, vp, vp]
     lib.ltmp2_learned_quadrature.argtypes = [vp, C.c_double, C.c_double, C.c_int, C.c_int,
                                              C.c_double, vp, vp, dp, C.POINTER(C.c_int), vp]
+    lib.ltmp2_remez_polish.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, vp,
+                                       vp, dp, C.POINTER(C.c_int)]
+    lib.ltmp2_remez_polish.restype = C.c_int
     lib.ltmp2_mlp_last_error.argtypes = []
     lib.ltmp2_mlp_last_error.restype = C.c_char_p
     for name in ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
@@ -213,6 +216,18 @@ def learned_quadrature(params, x_min, x_max, n_tau, polish_steps=3, cert_tol=1e-
         _ptr(np.ascontiguousarray(params, np.float32)), x_min, x_max, n_tau, polish_steps,
         cert_tol, _ptr(tau), _ptr(w), C.byref(d), C.byref(fl), C.c_void_p(_current_stream())))
     return tau, w, d.value, fl.value
+
+
+def remez_polish(x_min, x_max, tau, w, steps=3, cert_tol=1e-6):
+    """Host Remez polish of a proposal: (tau, w, delta, certified)."""
+    lib = load()
+    tau = np.array(tau, np.float64)
+    w = np.array(w, np.float64)
+    d = C.c_double()
+    ok = C.c_int()
+    _mcheck(lib, lib.ltmp2_remez_polish(x_min, x_max, len(tau), steps, cert_tol, _ptr(tau), _ptr(w),
+                                        C.byref(d), C.byref(ok)))
+    return tau, w, d.value, ok.value
 
 
 def write_mlp_weights(path, params):
