@@ -96,7 +96,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--quad", default="learned", choices=["plain", "learned"])
+    ap.add_argument("--no-fp64-reference", action="store_true",
+                    help="skip timing the plain FP64 form beside the headline form")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -116,12 +119,17 @@ def main():
     stream = torch.cuda.current_stream()
     t = time.time()
     prec = {"fp64": 0, "fp32": 1, "bf16x3": 2}[args.prec]
+    weights = os.path.join(ROOT, "paper_1611_06797_amd", "data", "laplace_mlp.bin")
+    t = time.time()
     ctx = Context(spec.L, spec.n, spec.ecut, spec.eaux, m, e, c, spec.n_occ, spec.n_tau,
-                  stream=stream.cuda_stream, prec=prec)
+                  stream=stream.cuda_stream, prec=prec,
+                  mlp_weights=weights if args.quad == "learned" else None)
     torch.cuda.synchronize()
+    t_setup = time.time() - t
     info = ctx.info
-    log(f"setup {time.time() - t:.1f}s: n_g={info.n_g} n_vir={info.n_vir} "
-        f"device {info.device_bytes / 2**30:.1f} GiB quad_delta={info.quad_delta:.3e}")
+    log(f"setup {t_setup:.1f}s: n_g={info.n_g} n_vir={info.n_vir} "
+        f"device {info.device_bytes / 2**30:.1f} GiB quad_delta={info.quad_delta:.3e} "
+        f"quad_flags={info.quad_flags}")
     for k in range(args.warmup):
         t = time.time()
         ctx.energy()
@@ -137,6 +145,27 @@ def main():
     timing = ctx.get_timing()
     ms_step = 1000.0 * dt / args.steps
     log("stage ms per step:", {k: round(v[0] / args.steps, 2) for k, v in timing.items()})
+    tau_used, w_used, _ = ctx.get_quadrature()
+    ctx.close()
+
+    # plain FP64 form on the same cell and the same quadrature (equal accuracy reference)
+    ref = None
+    if not args.no_fp64_reference and args.prec != "fp64":
+        ctx64 = Context(spec.L, spec.n, spec.ecut, spec.eaux, m, e, c, spec.n_occ, spec.n_tau,
+                        stream=stream.cuda_stream, prec=0, tau=tau_used, w=w_used)
+        ctx64.energy()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(args.steps):
+            ed64, ex64, _, _ = ctx64.energy()
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t1
+        ctx64.close()
+        ref = {"fp64_energies_per_s": args.steps / dt64, "speedup": dt64 / dt,
+               "dE_direct": ed - ed64, "dE_exchange": ex - ex64,
+               "tolerance": spec.n_occ * 1e-6}
+        log(f"plain fp64: {args.steps / dt64:.4f} energies/s; speedup {dt64 / dt:.2f}x; "
+            f"dE_d {ed - ed64:.2e} dE_x {ex - ex64:.2e}")
 
     # dominant kernel stage and its roofline
     dom = max(timing, key=lambda k: timing[k][0])
@@ -178,9 +207,12 @@ def main():
                                   f"E_cut={spec.ecut} Ha (n_pw={info.n_pw}), "
                                   f"E_aux={spec.eaux} Ha (n_g={info.n_g}), "
                                   f"n_occ={spec.n_occ}, n_tau={spec.n_tau}, seed={spec.seed}",
-                      "precision": args.prec, "quadrature": "plain minimax"},
+                      "precision": args.prec,
+                      "quadrature": "learned+3 Remez (certified)" if info.quad_flags & 1
+                      else "plain minimax"},
            "energy": {"e_direct": ed, "e_exchange": ex, "quad_delta": qe},
            "stage_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
+           "setup_s": t_setup, "fp64_reference": ref,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -260,6 +260,42 @@ ltmp2_status ltmp2_remez_polish(double x_min, double x_max, int n_tau, int steps
 /* Message of the last failed MLP / table call on this thread. */
 const char* ltmp2_mlp_last_error(void);
 
+/*
+ * Batched evaluation of many independent cells (grown form: many small cells
+ * of uneven size, each with its own Laplace grid).  Cells are grouped by FFT
+ * grid; per Laplace point and round of outer G', one persistent fused launch
+ * evaluates the Fock-like pair transforms of every cell of a group; the large
+ * scratch is pooled; a tuner picks the pair kernel's slab tile and resident
+ * workgroups per CU on first use; the launch sequence is captured into a
+ * hipGraph after the first (eager) evaluation and replayed afterwards.
+ * Per-cell arrays are as in ltmp2_setup; tau / w may be NULL (or hold NULL
+ * entries for cells without a given quadrature).  All cells must use the same
+ * precision.  If hip_stream is NULL the batch creates its own stream.
+ */
+typedef struct ltmp2_batch ltmp2_batch;
+
+typedef struct {
+  int n_cells, n_groups;
+  int graph_ready;        /* 1 once the launch sequence is captured          */
+  size_t device_bytes;
+} ltmp2_batch_stats;
+
+ltmp2_status ltmp2_batch_create(int n_cells, const ltmp2_params* params,
+                                const int32_t* const* miller, const double* const* eps,
+                                const double* const* coeff, const double* const* tau,
+                                const double* const* w, const char* mlp_weights,
+                                void* hip_stream, ltmp2_batch** out);
+/* e_direct, e_exchange [n_cells] (Ha per cell). */
+ltmp2_status ltmp2_batch_energy(ltmp2_batch* b, double* e_direct, double* e_exchange);
+ltmp2_status ltmp2_batch_info(const ltmp2_batch* b, ltmp2_batch_stats* stats);
+/* Group g: grid size, cells, rounds of outer G', tuned slab tile and
+ * workgroups per CU of the fused pair launch, tuned launch time (ms). */
+ltmp2_status ltmp2_batch_group(const ltmp2_batch* b, int g, int* n_fft, int* n_cells, int* rounds,
+                               int* slab_tile, int* wg_per_cu, double* tuned_ms);
+ltmp2_status ltmp2_batch_cell(const ltmp2_batch* b, int k, ltmp2_info* info);
+void ltmp2_batch_destroy(ltmp2_batch* b);
+const char* ltmp2_batch_last_error(const ltmp2_batch* b);
+
 /* Release a context and all of its device memory (NULL is ignored). */
 void ltmp2_destroy(ltmp2_ctx* ctx);
 

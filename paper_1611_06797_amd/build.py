@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libltmp2.so")
-GRIDS = (12, 32, 40)
+GRIDS = (12, 15, 16, 18, 20, 24, 25, 27, 30, 32, 40)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -46,7 +46,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     units = [("registry.hip", "registry.o", []),
              ("ltmp2.hip", "ltmp2.o", []),
              ("quadrature.cpp", "quadrature.o", ["-x", "hip"]),
-             ("mlp.hip", "mlp.o", [])]
+             ("mlp.hip", "mlp.o", []),
+             ("batch.hip", "batch.o", [])]
     units += [("grid_kernels.hip", f"grid_{n}.o", [f"-DLTMP2_N={n}"]) for n in GRIDS]
     cmds = []
     for src, obj, extra in units:

@@ -1,0 +1,82 @@
+// Internal state of an LTMP2 context (shared by the C ABI implementation
+// files; not part of the public header).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ltmp2.h"
+#include "dispatch.h"
+
+struct ltmp2_ctx {
+  bool own_scratch = true;  // false: chi / chihat / P / w belong to a batch
+  ltmp2_params prm{};
+  std::string err;
+  bool failed = false;
+  hipStream_t stream = nullptr;
+
+  // sizes
+  int n = 0, nr = 0, npw = 0, nst = 0, no = 0, nv = 0, ng = 0, nh = 0, ntau = 0, npairs = 0;
+  long nrp = 0;  // padded row stride of grid arrays (multiple of 64)
+  int kmax_aux = 0, kmax_orb = 0, gblock = 0;
+  double omega = 0, dV = 0, mu = 0, xmin = 0, xmax = 0, quad_delta = 0;
+  int quad_flags = 0;
+  std::string mlp_path;
+  std::vector<double> eps, tau, w;
+  std::vector<int> aux;  // [ng][3], H first then -H
+
+  // device tables
+  ltmp2::SphereCols sc{};
+  int* d_cdesc = nullptr;
+  int* d_cstart = nullptr;
+  int* d_ckx = nullptr;
+  int* d_wq = nullptr;
+  signed char* d_wsgn = nullptr;
+  int* d_gdesc = nullptr;
+  int* d_pairs = nullptr;
+  double* d_v = nullptr;
+  double* d_fo = nullptr;  // [ntau][no]
+  double* d_fv = nullptr;  // [ntau][nv]
+
+  // device data, element type double (FP64) or float (FP32, BF16X3)
+  size_t esz = sizeof(double);
+  void* d_psi = nullptr;       // [nst][nrp]
+  void* d_nd = nullptr;        // [nv][nh][no] complex
+  void* d_bpw = nullptr;       // [nv][npw] real basis of virtual coefficients
+  void* d_chi = nullptr;       // [nrp][nrp]
+  void* d_chihat = nullptr;    // [nh][nrp] complex
+  double* d_pd = nullptr;      // [nh]
+  void* d_P = nullptr;         // [gblock * no * 2][npw]
+  void* d_w = nullptr;         // [gblock * no][nrp] complex
+  double* d_xpart = nullptr;   // [nh][npairs]
+  double* d_scal = nullptr;    // [2 * ntau + 8] device scalars
+
+  std::vector<void*> owned;
+  size_t bytes = 0;
+
+  // optional per-stage event timing
+  bool timing = false;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  double stage_ms[8] = {0};
+  long stage_n[8] = {0};
+};
+
+namespace ltmp2 {
+// Host drivers of one Laplace point (ltmp2.hip); values land in d_scal.
+ltmp2_status run_direct(ltmp2_ctx* c, int itau, double* chi_out);
+ltmp2_status run_exchange(ltmp2_ctx* c, int itau, int g_first, int g_count);
+// Pieces of run_exchange used by batched execution.
+ltmp2_status exchange_block_prepare(ltmp2_ctx* c, int itau, int g0, int gb);
+ltmp2_status exchange_reduce(ltmp2_ctx* c, int itau, int g_first, int g_count);
+ltmp2_status setup_cell(ltmp2_ctx* c, const int32_t* miller, const double* eps,
+                        const double* coeff, const double* tau, const double* w);
+ltmp2_status validate_inputs(const ltmp2_params* p, const int32_t* miller, const double* eps,
+                             const double* coeff, const double* tau, const double* w);
+const std::string& setup_error();
+}  // namespace ltmp2

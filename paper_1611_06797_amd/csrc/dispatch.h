@@ -35,6 +35,10 @@ struct GridOps {
   ltmp2_status (*pair)(const T* psi, long ld, const cplx<T>* w, int no, const int* pairs,
                        int npairs, int gb, const int* gdesc, int ng, const double* v, int kmax,
                        double dV2, double* xpart, hipStream_t st);
+  // persistent multi-cell pair launch (device arrays cells[ncells], prefix[ncells + 1])
+  ltmp2_status (*pair_multi)(const PairCell* cells, const long* prefix, int ncells, int ng_max,
+                             int kmax_max, int sx, int nblocks, hipStream_t st);
+  int (*pair_sx_max)(int kmax);
 };
 
 template <class T>

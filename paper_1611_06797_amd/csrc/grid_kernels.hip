@@ -1,6 +1,9 @@
 // Transform kernels instantiated for one grid size n = LTMP2_N.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "dispatch.h"
 
 #ifndef LTMP2_N
@@ -20,13 +23,26 @@ int choose_sx(int nk) {
   return sx;
 }
 
+// Dynamic shared memory above the default needs a per-kernel attribute; set
+// it once per kernel (never while a stream is being captured into a graph).
+bool ensure_lds(const void* kern, size_t lds) {
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = done.find(kern);
+  if (it != done.end() && it->second >= lds) return true;
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) !=
+      hipSuccess)
+    return false;
+  done[kern] = lds;
+  return true;
+}
+
 template <class K>
 ltmp2_status launch(K kern, dim3 grid, size_t lds, hipStream_t st, auto... args) {
   if (lds > kLdsCap) return LTMP2_EINVAL;
   if (grid.x == 0 || grid.y == 0) return LTMP2_OK;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-  if (e != hipSuccess) return LTMP2_EDEVICE;
+  if (!ensure_lds(reinterpret_cast<const void*>(kern), lds)) return LTMP2_EDEVICE;
   hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, args...);
   return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
 }
@@ -128,10 +144,10 @@ struct PairF {
                            int npairs, int gb, const int* gdesc, int ng, const double* v, int kmax,
                            double dV2, double* xpart, hipStream_t st) {
       const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
+      PairCell pc{psi, w, pairs, gdesc, v, xpart, ld, no, npairs, gb, ng, kmax, dV2};
       const long total = long(npairs) * gb;
       const unsigned nblk = unsigned((total + 7) / 8 * 8);
-      return launch(k_pair<T, N, OPT>, dim3(nblk), slab_lds_bytes<T>(N, nk, sx), st, psi, ld, w,
-                    no, pairs, npairs, gb, gdesc, ng, v, kmax, sx, dV2, xpart);
+      return launch(k_pair<T, N, OPT>, dim3(nblk), slab_lds_bytes<T>(N, nk, sx), st, pc, sx);
     }
   };
 };
@@ -141,6 +157,31 @@ ltmp2_status pair(const T* psi, long ld, const cplx<T>* w, int no, const int* pa
                   double* xpart, hipStream_t st) {
   return by_opt<PairF<T>::template F>(ng, psi, ld, w, no, pairs, npairs, gb, gdesc, ng, v, kmax,
                                       dV2, xpart, st);
+}
+
+template <class T>
+struct PairMultiF {
+  template <int OPT>
+  struct F {
+    static ltmp2_status go(const PairCell* cells, const long* prefix, int ncells, int kmax_max,
+                           int sx, int nblocks, hipStream_t st) {
+      const int nk = 2 * kmax_max + 1;
+      return launch(k_pair_multi<T, N, OPT>, dim3(unsigned(nblocks)), slab_lds_bytes<T>(N, nk, sx),
+                    st, cells, prefix, ncells, sx);
+    }
+  };
+};
+template <class T>
+ltmp2_status pair_multi(const PairCell* cells, const long* prefix, int ncells, int ng_max,
+                        int kmax_max, int sx, int nblocks, hipStream_t st) {
+  return by_opt<PairMultiF<T>::template F>(ng_max, cells, prefix, ncells, kmax_max, sx, nblocks,
+                                           st);
+}
+
+// Largest slab group of the pair transform that fits the shared memory.
+template <class T>
+int pair_sx_max(int kmax) {
+  return choose_sx<T>(2 * kmax + 1);
 }
 
 // Explicit instantiation in both compilation passes, so the device pass
@@ -158,7 +199,10 @@ ltmp2_status pair(const T* psi, long ld, const cplx<T>* w, int no, const int* pa
                                    int, double, cplx<T>*, long, hipStream_t);                  \
   template ltmp2_status pair<T>(const T*, long, const cplx<T>*, int, const int*, int, int,     \
                                 const int*, int, const double*, int, double, double*,          \
-                                hipStream_t);
+                                hipStream_t);                                                  \
+  template ltmp2_status pair_multi<T>(const PairCell*, const long*, int, int, int, int, int,   \
+                                      hipStream_t);                                            \
+  template int pair_sx_max<T>(int);
 LTMP2_INST(double)
 LTMP2_INST(float)
 
@@ -171,10 +215,10 @@ extern const GridOps<double> LTMP2_CAT(kGridOpsD_, LTMP2_N);
 extern const GridOps<float> LTMP2_CAT(kGridOpsF_, LTMP2_N);
 const GridOps<double> LTMP2_CAT(kGridOpsD_, LTMP2_N) = {
     orbitals<double>, overlap<double>, chi_rows<double>, chi_cols<double>, wstates<double>,
-    pair<double>};
+    pair<double>, pair_multi<double>, pair_sx_max<double>};
 const GridOps<float> LTMP2_CAT(kGridOpsF_, LTMP2_N) = {
     orbitals<float>, overlap<float>, chi_rows<float>, chi_cols<float>, wstates<float>,
-    pair<float>};
+    pair<float>, pair_multi<float>, pair_sx_max<float>};
 #endif
 
 }  // namespace ltmp2

@@ -224,39 +224,39 @@ __global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, i
 //         = sum_G v(G) |A_ii|^2                               (i = j).
 // Summed over pairs this is S_x(G') = sum_G v(G) sum_ij A_ij(G) A^{(-G')}_ji(-G),
 // using A^{(-G')}_ji(-G) = conj A^{(G')}_ji(G) for real orbitals.
+
+// Everything one cell contributes to a pair launch.
+struct PairCell {
+  const void* psi;     // [nocc..][ld] orbitals (T)
+  const void* w;       // [gb][nocc][ld] transformed states (cplx<T>)
+  const int* pairs;    // [npairs] i | j << 16
+  const int* gdesc;    // [ng]
+  const double* v;     // [ng]
+  double* xpart;       // [gb][npairs] partial sums of this block
+  long ld;
+  int nocc, npairs, gb, ng, kmax;
+  double dV2;
+};
+
 template <class T, int N, int OPT>
-__global__ __launch_bounds__(kThreads) void k_pair(const T* __restrict__ psi, long ld,
-                                                   const cplx<T>* __restrict__ w, int nocc,
-                                                   const int* __restrict__ pairs, int npairs,
-                                                   int gb, const int* __restrict__ gdesc_all,
-                                                   int ng, const double* __restrict__ v, int kmax,
-                                                   int sx, double dV2,
-                                                   double* __restrict__ xpart) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ double red[kThreads / 64];
-  const int nk = 2 * kmax + 1;
+__device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void* smem,
+                                 double* red) {
+  const int nk = 2 * pc.kmax + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, -1>(L.tw, N);
-  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous range of the (G', pair) list, pairs in i-major order, so the
-  // workgroups resident on one XCD share (G', i) and psi_i, w_i stay in its L2.
-  const long total = long(npairs) * gb;
-  const long per_xcd = (total + 7) / 8;
-  const long t = long(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (t >= total) return;
-  const int gl = int(t / npairs);
-  const int p = int(t - long(gl) * npairs);
-  const int i = pairs[p] & 0xffff, j = pairs[p] >> 16;
-  const T* pi = psi + long(i) * ld;
-  const T* pj = psi + long(j) * ld;
-  const cplx<T>* wi = w + (long(gl) * nocc + i) * ld;
-  const cplx<T>* wj = w + (long(gl) * nocc + j) * ld;
+  const int i = pc.pairs[p] & 0xffff, j = pc.pairs[p] >> 16;
+  const T* psi = static_cast<const T*>(pc.psi);
+  const cplx<T>* w = static_cast<const cplx<T>*>(pc.w);
+  const T* pi = psi + long(i) * pc.ld;
+  const T* pj = psi + long(j) * pc.ld;
+  const cplx<T>* wi = w + (long(gl) * pc.nocc + i) * pc.ld;
+  const cplx<T>* wj = w + (long(gl) * pc.nocc + j) * pc.ld;
   int gd[OPT];
   cplx<T> acc[2][OPT];
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
     const int o = threadIdx.x + t * kThreads;
-    gd[t] = (o < ng) ? gdesc_all[o] : 0;
+    gd[t] = (o < pc.ng) ? pc.gdesc[o] : 0;
     acc[0][t] = {T(0), T(0)};
     acc[1][t] = {T(0), T(0)};
   }
@@ -267,23 +267,67 @@ __global__ __launch_bounds__(kThreads) void k_pair(const T* __restrict__ psi, lo
     const cplx<T> b = (f == 0) ? wj[r] : wi[r];
     return cplx<T>{a * b.x, a * b.y};
   };
-  forward_pruned<T, -1, N, 2, OPT>(ld_, (i == j) ? 1 : 2, kmax, sx, gd, ng, acc, L);
+  forward_pruned<T, -1, N, 2, OPT>(ld_, (i == j) ? 1 : 2, pc.kmax, sx, gd, pc.ng, acc, L);
   double s = 0.0;
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
     const int o = threadIdx.x + t * kThreads;
-    if (o < ng) {
+    if (o < pc.ng) {
       const double ar = acc[0][t].x, ai = acc[0][t].y;
       if (i == j) {
-        s += v[o] * (ar * ar + ai * ai);
+        s += pc.v[o] * (ar * ar + ai * ai);
       } else {
         const double br = acc[1][t].x, bi = acc[1][t].y;
-        s += 2.0 * v[o] * (ar * br + ai * bi);
+        s += 2.0 * pc.v[o] * (ar * br + ai * bi);
       }
     }
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) xpart[long(gl) * npairs + p] = dV2 * s;
+  if (threadIdx.x == 0) pc.xpart[long(gl) * pc.npairs + p] = pc.dV2 * s;
+}
+
+// One cell: workgroups are dispatched round-robin over the 8 XCDs; each XCD
+// gets a contiguous range of the (G', pair) list, pairs in i-major order, so
+// the workgroups resident on one XCD share (G', i) and psi_i, w_i stay in L2.
+template <class T, int N, int OPT>
+__global__ __launch_bounds__(kThreads) void k_pair(PairCell pc, int sx) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double red[kThreads / 64];
+  const long total = long(pc.npairs) * pc.gb;
+  const long per_xcd = (total + 7) / 8;
+  const long t = long(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= total) return;
+  const int gl = int(t / pc.npairs);
+  pair_item<T, N, OPT>(pc, gl, int(t - long(gl) * pc.npairs), sx, smem, red);
+}
+
+// Several cells of the same grid in one persistent launch: the work list is
+// the concatenation of every cell's (G', pair) items (prefix[c] = first item
+// of cell c); each XCD owns a contiguous range and its workgroups stride
+// through it, so every workgroup exits after a bounded number of items.
+template <class T, int N, int OPT>
+__global__ __launch_bounds__(kThreads) void k_pair_multi(const PairCell* __restrict__ cells,
+                                                         const long* __restrict__ prefix,
+                                                         int ncells, int sx) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double red[kThreads / 64];
+  const long total = prefix[ncells];
+  const long per_xcd = (total + 7) / 8;
+  const long stride = gridDim.x / 8;
+  for (long q = blockIdx.x / 8; q < per_xcd; q += stride) {
+    const long t = long(blockIdx.x % 8) * per_xcd + q;
+    if (t >= total) break;
+    int lo = 0, hi = ncells - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const PairCell pc = cells[lo];
+    const long u = t - prefix[lo];
+    const int gl = int(u / pc.npairs);
+    pair_item<T, N, OPT>(pc, gl, int(u - long(gl) * pc.npairs), sx, smem, red);
+    __syncthreads();
+  }
 }
 
 }  // namespace ltmp2

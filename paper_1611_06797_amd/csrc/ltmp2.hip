@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/ltmp2.h"
+#include "ctx.h"
 #include "dispatch.h"
 #include "quadrature.h"
 
@@ -28,62 +29,7 @@ struct DevBuf {
 
 }  // namespace
 
-struct ltmp2_ctx {
-  ltmp2_params prm{};
-  std::string err;
-  bool failed = false;
-  hipStream_t stream = nullptr;
 
-  // sizes
-  int n = 0, nr = 0, npw = 0, nst = 0, no = 0, nv = 0, ng = 0, nh = 0, ntau = 0, npairs = 0;
-  long nrp = 0;  // padded row stride of grid arrays (multiple of 64)
-  int kmax_aux = 0, kmax_orb = 0, gblock = 0;
-  double omega = 0, dV = 0, mu = 0, xmin = 0, xmax = 0, quad_delta = 0;
-  int quad_flags = 0;
-  std::string mlp_path;
-  std::vector<double> eps, tau, w;
-  std::vector<int> aux;  // [ng][3], H first then -H
-
-  // device tables
-  SphereCols sc{};
-  int* d_cdesc = nullptr;
-  int* d_cstart = nullptr;
-  int* d_ckx = nullptr;
-  int* d_wq = nullptr;
-  signed char* d_wsgn = nullptr;
-  int* d_gdesc = nullptr;
-  int* d_pairs = nullptr;
-  double* d_v = nullptr;
-  double* d_fo = nullptr;  // [ntau][no]
-  double* d_fv = nullptr;  // [ntau][nv]
-
-  // device data, element type double (FP64) or float (FP32, BF16X3)
-  size_t esz = sizeof(double);
-  void* d_psi = nullptr;       // [nst][nrp]
-  void* d_nd = nullptr;        // [nv][nh][no] complex
-  void* d_bpw = nullptr;       // [nv][npw] real basis of virtual coefficients
-  void* d_chi = nullptr;       // [nrp][nrp]
-  void* d_chihat = nullptr;    // [nh][nrp] complex
-  double* d_pd = nullptr;      // [nh]
-  void* d_P = nullptr;         // [gblock * no * 2][npw]
-  void* d_w = nullptr;         // [gblock * no][nrp] complex
-  double* d_xpart = nullptr;   // [nh][npairs]
-  double* d_scal = nullptr;    // [2 * ntau + 8] device scalars
-
-  std::vector<void*> owned;
-  size_t bytes = 0;
-
-  // optional per-stage event timing
-  bool timing = false;
-  struct Mark {
-    int stage;
-    hipEvent_t a, b;
-  };
-  std::vector<Mark> marks;
-  std::vector<hipEvent_t> pool;
-  double stage_ms[8] = {0};
-  long stage_n[8] = {0};
-};
 
 namespace {
 
@@ -548,11 +494,12 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
   if ((s = upload(c, &d_coef, coef_col))) return s;
   if ((s = dalloc_bytes(c, &c->d_psi, es * size_t(c->nst) * nrp)) ||
       (s = dalloc_bytes(c, &c->d_nd, es * 2 * size_t(c->nv) * c->nh * c->no)) ||
-      (s = dalloc_bytes(c, &c->d_chi, es * nrp * nrp)) ||
-      (s = dalloc_bytes(c, &c->d_chihat, es * 2 * size_t(c->nh) * nrp)) ||
+      (c->own_scratch && (s = dalloc_bytes(c, &c->d_chi, es * nrp * nrp))) ||
+      (c->own_scratch && (s = dalloc_bytes(c, &c->d_chihat, es * 2 * size_t(c->nh) * nrp))) ||
       (s = dalloc(c, &c->d_pd, c->nh)) ||
-      (s = dalloc_bytes(c, &c->d_P, es * 2 * size_t(c->gblock) * c->no * c->npw)) ||
-      (s = dalloc_bytes(c, &c->d_w, es * 2 * size_t(c->gblock) * c->no * nrp)) ||
+      (c->own_scratch &&
+       (s = dalloc_bytes(c, &c->d_P, es * 2 * size_t(c->gblock) * c->no * c->npw))) ||
+      (c->own_scratch && (s = dalloc_bytes(c, &c->d_w, es * 2 * size_t(c->gblock) * c->no * nrp))) ||
       (s = dalloc(c, &c->d_xpart, size_t(c->nh) * c->npairs)) ||
       (s = dalloc(c, &c->d_scal, 2 * size_t(c->ntau) + 8)))
     return s;
@@ -610,7 +557,7 @@ ltmp2_status run_direct_t(ltmp2_ctx* c, int itau, double* chi_out) {
   return check_launch(c, "k_reduce_direct");
 }
 
-ltmp2_status run_direct(ltmp2_ctx* c, int itau, double* chi_out) {
+ltmp2_status direct_tau(ltmp2_ctx* c, int itau, double* chi_out) {
   switch (c->prm.prec) {
     case LTMP2_FP64: return run_direct_t<double, kF64>(c, itau, chi_out);
     case LTMP2_FP32: return run_direct_t<float, kF32>(c, itau, chi_out);
@@ -618,49 +565,68 @@ ltmp2_status run_direct(ltmp2_ctx* c, int itau, double* chi_out) {
   }
 }
 
-// exchange term at one Laplace point for G' in H[g_first, g_first + g_count)
+// transformed states of one block of outer G' (GEMM P = C Psi_v, synthesis of w)
 template <class T, int MODE>
-ltmp2_status run_exchange_t(ltmp2_ctx* c, int itau, int g_first, int g_count) {
+ltmp2_status block_prepare_t(ltmp2_ctx* c, int itau, int g0, int gb) {
   ltmp2_status s;
   const GridOps<T>* ops = grid_ops<T>(c->n);
   const double* fo = c->d_fo + size_t(itau) * c->no;
   const double* fv = c->d_fv + size_t(itau) * c->nv;
   const long lda = 2L * c->nh * c->no;
-  for (int g0 = g_first; g0 < g_first + g_count; g0 += c->gblock) {
-    const int gb = std::min(c->gblock, g_first + g_count - g0);
-    const int M = 2 * gb * c->no;
-    // P = C Psi_v in the real basis:  C_ja = fo_j fv_a n_aj(G')
-    {
-      StageTimer tm(c, 3);
-      s = launch_gemm_kmajor<MODE>(static_cast<const T*>(c->d_nd) + 2L * g0 * c->no, lda,
-                                   c->d_bpw, (long)c->npw, c->d_P, (long)c->npw, M, c->npw, c->nv,
-                                   fv, fo, 2, c->no, c->stream);
-    }
-    if (s) return fail(c, s, "transformed-state GEMM launch failed");
-    {
-      StageTimer tm(c, 4);
-      s = ops->wstates(static_cast<const T*>(c->d_P), c->npw, c->d_wq, c->d_wsgn, c->sc, gb * c->no,
-                       1.0 / std::sqrt(c->omega), static_cast<cplx<T>*>(c->d_w), c->nrp,
-                       c->stream);
-    }
-    if (s) return fail(c, s, "transformed-state launch failed");
-    {
-      StageTimer tm(c, 5);
-      s = ops->pair(static_cast<const T*>(c->d_psi), c->nrp, static_cast<const cplx<T>*>(c->d_w),
-                    c->no, c->d_pairs, c->npairs, gb, c->d_gdesc, c->ng, c->d_v, c->kmax_aux,
-                    c->dV * c->dV, c->d_xpart + size_t(g0) * c->npairs, c->stream);
-    }
-    if (s) return fail(c, s, "pair transform launch failed");
+  const int M = 2 * gb * c->no;
+  // P = C Psi_v in the real basis:  C_ja = fo_j fv_a n_aj(G')
+  {
+    StageTimer tm(c, 3);
+    s = launch_gemm_kmajor<MODE>(static_cast<const T*>(c->d_nd) + 2L * g0 * c->no, lda, c->d_bpw,
+                                 (long)c->npw, c->d_P, (long)c->npw, M, c->npw, c->nv, fv, fo, 2,
+                                 c->no, c->stream);
   }
+  if (s) return fail(c, s, "transformed-state GEMM launch failed");
+  {
+    StageTimer tm(c, 4);
+    s = ops->wstates(static_cast<const T*>(c->d_P), c->npw, c->d_wq, c->d_wsgn, c->sc, gb * c->no,
+                     1.0 / std::sqrt(c->omega), static_cast<cplx<T>*>(c->d_w), c->nrp, c->stream);
+  }
+  if (s) return fail(c, s, "transformed-state launch failed");
+  return LTMP2_OK;
+}
+
+template <class T>
+ltmp2_status block_pair_t(ltmp2_ctx* c, int g0, int gb) {
+  const GridOps<T>* ops = grid_ops<T>(c->n);
+  StageTimer tm(c, 5);
+  ltmp2_status s = ops->pair(static_cast<const T*>(c->d_psi), c->nrp,
+                             static_cast<const cplx<T>*>(c->d_w), c->no, c->d_pairs, c->npairs, gb,
+                             c->d_gdesc, c->ng, c->d_v, c->kmax_aux, c->dV * c->dV,
+                             c->d_xpart + size_t(g0) * c->npairs, c->stream);
+  if (s) return fail(c, s, "pair transform launch failed");
+  return LTMP2_OK;
+}
+
+ltmp2_status reduce_x(ltmp2_ctx* c, int itau, int g_first, int g_count) {
   StageTimer tm(c, 6);
   hipLaunchKernelGGL(k_reduce_exchange, dim3(1), dim3(256), 0, c->stream, c->d_xpart, g_first,
                      g_count, c->npairs, c->d_v, c->d_scal + 2 * itau + 1);
   return check_launch(c, "k_reduce_exchange");
 }
 
-ltmp2_status run_exchange(ltmp2_ctx* c, int itau, int g_first, int g_count) {
-  if (c->prm.prec == LTMP2_FP64) return run_exchange_t<double, kF64>(c, itau, g_first, g_count);
-  return run_exchange_t<float, kF32>(c, itau, g_first, g_count);
+ltmp2_status block_prepare(ltmp2_ctx* c, int itau, int g0, int gb) {
+  switch (c->prm.prec) {
+    case LTMP2_FP64: return block_prepare_t<double, kF64>(c, itau, g0, gb);
+    default: return block_prepare_t<float, kF32>(c, itau, g0, gb);
+  }
+}
+
+// exchange term at one Laplace point for G' in H[g_first, g_first + g_count)
+ltmp2_status exchange_tau(ltmp2_ctx* c, int itau, int g_first, int g_count) {
+  ltmp2_status s;
+  for (int g0 = g_first; g0 < g_first + g_count; g0 += c->gblock) {
+    const int gb = std::min(c->gblock, g_first + g_count - g0);
+    if ((s = block_prepare(c, itau, g0, gb))) return s;
+    s = (c->prm.prec == LTMP2_FP64) ? block_pair_t<double>(c, g0, gb) : block_pair_t<float>(c, g0, gb);
+    if (s) return s;
+  }
+  return reduce_x(c, itau, g_first, g_count);
 }
 
 // G_occ / G_vir rows into double buffers (float contexts go through chi as scratch)
@@ -690,6 +656,30 @@ ltmp2_status green_t(ltmp2_ctx* c, int itau, int row0, int nrows, double* gocc, 
 }
 
 }  // namespace
+
+namespace ltmp2 {
+ltmp2_status run_direct(ltmp2_ctx* c, int itau, double* chi_out) {
+  return direct_tau(c, itau, chi_out);
+}
+ltmp2_status run_exchange(ltmp2_ctx* c, int itau, int g_first, int g_count) {
+  return exchange_tau(c, itau, g_first, g_count);
+}
+ltmp2_status exchange_block_prepare(ltmp2_ctx* c, int itau, int g0, int gb) {
+  return block_prepare(c, itau, g0, gb);
+}
+ltmp2_status exchange_reduce(ltmp2_ctx* c, int itau, int g_first, int g_count) {
+  return reduce_x(c, itau, g_first, g_count);
+}
+ltmp2_status setup_cell(ltmp2_ctx* c, const int32_t* miller, const double* eps,
+                        const double* coeff, const double* tau, const double* w) {
+  return setup_impl(c, miller, eps, coeff, tau, w);
+}
+ltmp2_status validate_inputs(const ltmp2_params* p, const int32_t* miller, const double* eps,
+                             const double* coeff, const double* tau, const double* w) {
+  return validate(p, miller, eps, coeff, tau, w);
+}
+const std::string& setup_error() { return g_setup_error; }
+}  // namespace ltmp2
 
 extern "C" ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller,
                                     const double* eps, const double* coeff, const double* tau,
@@ -733,7 +723,7 @@ extern "C" ltmp2_status ltmp2_green(ltmp2_ctx* c, int itau, int row0, int nrows,
 extern "C" ltmp2_status ltmp2_chi(ltmp2_ctx* c, int itau, void* chi_GG_dev, double* e_direct_tau) {
   ltmp2_status s = usable(c, itau);
   if (s) return s;
-  if ((s = run_direct(c, itau, reinterpret_cast<double*>(chi_GG_dev)))) return s;
+  if ((s = direct_tau(c, itau, reinterpret_cast<double*>(chi_GG_dev)))) return s;
   double v = 0.0;
   HIPCHK(c, hipMemcpyAsync(&v, c->d_scal + 2 * itau, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -751,7 +741,7 @@ extern "C" ltmp2_status ltmp2_exchange(ltmp2_ctx* c, int itau, int g_first, int 
     g_count = c->nh;
   }
   if (g_first < 0 || g_first + g_count > c->nh) return fail(c, LTMP2_EINVAL, "G' range outside H");
-  if ((s = run_exchange(c, itau, g_first, g_count))) return s;
+  if ((s = exchange_tau(c, itau, g_first, g_count))) return s;
   double v = 0.0;
   HIPCHK(c, hipMemcpyAsync(&v, c->d_scal + 2 * itau + 1, sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
@@ -766,8 +756,8 @@ extern "C" ltmp2_status ltmp2_energy(ltmp2_ctx* c, double* e_direct, double* e_e
   ltmp2_status s = usable(c, 0);
   if (s) return s;
   for (int t = 0; t < c->ntau; ++t) {
-    if ((s = run_direct(c, t, nullptr))) return s;
-    if ((s = run_exchange(c, t, 0, c->nh))) return s;
+    if ((s = direct_tau(c, t, nullptr))) return s;
+    if ((s = exchange_tau(c, t, 0, c->nh))) return s;
   }
   std::vector<double> pt(2 * size_t(c->ntau));
   HIPCHK(c, hipMemcpyAsync(pt.data(), c->d_scal, sizeof(double) * pt.size(), hipMemcpyDeviceToHost,

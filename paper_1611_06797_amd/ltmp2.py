@@ -25,7 +25,9 @@ EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_
             "ltmp2_destroy", "ltmp2_last_error", "ltmp2_supported_grids", "ltmp2_set_timing",
             "ltmp2_get_timing", "ltmp2_mlp_init", "ltmp2_quadrature_table", "ltmp2_mlp_dataset",
             "ltmp2_mlp_forward", "ltmp2_mlp_grad", "ltmp2_mlp_train", "ltmp2_learned_quadrature",
-            "ltmp2_mlp_last_error", "ltmp2_remez_polish")
+            "ltmp2_mlp_last_error", "ltmp2_remez_polish", "ltmp2_batch_create",
+            "ltmp2_batch_energy", "ltmp2_batch_info", "ltmp2_batch_group", "ltmp2_batch_cell",
+            "ltmp2_batch_destroy", "ltmp2_batch_last_error")
 MLP_NPARAM = 5976
 STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
 
