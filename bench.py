@@ -89,12 +89,139 @@ def cpu_baseline(spec, m, e, c, budget_s=25.0):
                       f"{no} x densities + {no}^2 x pair = {full:.0f}s"}
 
 
+def roofline(timing, work_of, steps, prec):
+    """Roofline entry of the dominant stage: work_of(stage) -> (flops, bytes) per step."""
+    dom = max(timing, key=lambda k: timing[k][0])
+    ms_tot, launches = timing[dom]
+    flops, byts = work_of(dom)
+    per_launch_s = ms_tot / 1000.0 / max(launches, 1)
+    if flops is not None:
+        ach = flops * steps / max(launches, 1) / per_launch_s
+        if dom in ("pair", "w_synth"):
+            peak, bound = (PEAK_FP64 if prec == "fp64" else PEAK_FP32), "alu"
+        else:
+            peak = {"fp64": PEAK_FP64, "fp32": PEAK_FP32, "bf16x3": PEAK_BF16}[prec]
+            if dom == "w_gemm" and prec == "bf16x3":
+                peak = PEAK_FP32
+            bound = "mfma"
+        roof = {"bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None}
+    else:
+        ach = byts * steps / max(launches, 1) / per_launch_s
+        roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": ach / PEAK_HBM, "traffic": None}
+    roof["kernel"] = dom
+    roof["launches_per_step"] = launches / steps
+    roof["mean_launch_ms"] = 1000.0 * per_launch_s
+    return roof
+
+
+def bench_batch(args):
+    """64 independent cells of uneven size per step (graph replay), cells/s."""
+    import numpy as np
+    import torch
+    from synthetic import batch_specs, make_cell
+    from paper_1611_06797_amd import Batch
+
+    specs = batch_specs()
+    t = time.time()
+    data = [make_cell(s) for s in specs]
+    log(f"{len(specs)} cells ready ({time.time() - t:.1f}s)")
+    torch.cuda.set_device(0)
+    prec = {"fp64": 0, "fp32": 1, "bf16x3": 2}[args.prec]
+    weights = os.path.join(ROOT, "paper_1611_06797_amd", "data", "laplace_mlp.bin")
+    cells = [dict(L=s.L, n_fft=s.n, ecut=s.ecut, eaux=s.eaux, miller=m, eps=e, coeff=c,
+                  n_occ=s.n_occ, n_tau=s.n_tau) for s, (m, e, c) in zip(specs, data)]
+    t = time.time()
+    b = Batch(cells, prec=prec, mlp_weights=weights if args.quad == "learned" else None,
+              stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    t_setup = time.time() - t
+    st = b.stats()
+    log(f"setup {t_setup:.1f}s: {st.n_groups} groups, device {st.device_bytes / 2**30:.1f} GiB")
+    # first call tunes and runs eagerly, the second captures the graph
+    warm = max(args.warmup, 2)
+    for k in range(warm):
+        t = time.time()
+        b.energy()
+        log(f"warmup {k}: {time.time() - t:.2f}s graph_ready={b.stats().graph_ready}")
+    groups = [b.group(g) for g in range(st.n_groups)]
+    log("groups:", groups)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ed, ex = b.energy()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"{args.steps} steps: {dt:.3f}s; sum E = {float(np.sum(ed + ex)):.10f}")
+    # one more (eager, event-timed) evaluation for the per-stage roofline
+    b.set_timing(True)
+    ed_t, ex_t = b.energy()
+    timing = b.get_timing()
+    b.set_timing(False)
+    log("stage ms (eager timed pass):", {k: round(v[0], 2) for k, v in timing.items()})
+    infos = [b.cell_info(k) for k in range(len(specs))]
+    b.close()
+
+    def work_of(stage):
+        fl, by = 0.0, 0.0
+        for inf, s in zip(infos, specs):
+            f1, b1 = stage_work(inf, s.n, stage)
+            fl = fl + f1 if f1 is not None else None
+            by = by + b1 if b1 is not None else None
+        return (fl if fl else None), (by if by else None)
+
+    roof = roofline(timing, work_of, 1, args.prec)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)...")
+        cpu = cpu_baseline_batch(specs, data, infos)
+    out = {"metric": "LTMP2 energies/sec", "value": len(specs) * args.steps / dt,
+           "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": warm,
+           "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None,
+           "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}[args.prec],
+           "data": "synthetic",
+           "config": {"workload": f"{len(specs)} independent gamma-only LTMP2 cells, "
+                                  "L~U[6,14] bohr, grids 15-30, E_cut=7.5 Ha, E_aux=5 Ha, "
+                                  "N_occ=round(8+5(L-6)), N_tau~U{6..12}, batch seed 0",
+                      "precision": args.prec,
+                      "quadrature": "learned+3 Remez" if args.quad == "learned" else "plain",
+                      "groups": groups},
+           "energy": {"sum_e_direct": float(np.sum(ed)), "sum_e_exchange": float(np.sum(ex)),
+                      "timed_pass_max_diff": float(max(np.abs(ed_t - ed).max(),
+                                                       np.abs(ex_t - ex).max()))},
+           "stage_ms_eager_pass": {k: v[0] for k, v in timing.items()},
+           "setup_s": t_setup, "roofline": roof, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(specs, data, infos):
+    """Oracle time per cell on three sampled cells, spread over the batch by
+    the pair-transform operation count (which dominates the oracle too)."""
+    order = sorted(range(len(specs)), key=lambda k: specs[k].L)
+    picks = [order[0], order[len(order) // 2], order[-1]]
+    ratios, notes = [], []
+    for k in picks:
+        r = cpu_baseline(specs[k], *data[k])
+        t_full = 1.0 / r["value"]
+        w = stage_work(infos[k], specs[k].n, "pair")[0]
+        ratios.append(t_full / w)
+        notes.append(f"cell {k} (n={specs[k].n}, N_occ={specs[k].n_occ}): {t_full:.0f}s")
+    c = sum(ratios) / len(ratios)
+    total = c * sum(stage_work(inf, s.n, "pair")[0] for inf, s in zip(infos, specs))
+    return {"value": len(specs) / total, "unit": "cells/s", "cores": r["cores"], "kind": "oracle",
+            "sample": "oracle full-energy estimates (occupied subset {HOMO}, scaled) of cells "
+                      + ", ".join(notes) + f"; batch total {total:.0f}s by pair operation count"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"],
+                    help="c1/c2/c3 single cells; c4 the 64-cell batch (cells/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--quad", default="learned", choices=["plain", "learned"])
@@ -104,6 +231,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.config == "c4":
+        return bench_batch(args)
 
     import numpy as np
     import torch

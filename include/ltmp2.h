@@ -288,6 +288,11 @@ ltmp2_status ltmp2_batch_create(int n_cells, const ltmp2_params* params,
 /* e_direct, e_exchange [n_cells] (Ha per cell). */
 ltmp2_status ltmp2_batch_energy(ltmp2_batch* b, double* e_direct, double* e_exchange);
 ltmp2_status ltmp2_batch_info(const ltmp2_batch* b, ltmp2_batch_stats* stats);
+/* Stage timing as for a single context, summed over cells; stage 5 times
+ * the fused multi-cell pair launches.  While timing is on, evaluations run
+ * eagerly (not from the captured graph) so that launches can be bracketed. */
+ltmp2_status ltmp2_batch_set_timing(ltmp2_batch* b, int on);
+ltmp2_status ltmp2_batch_get_timing(ltmp2_batch* b, int stage, double* ms, long* launches);
 /* Group g: grid size, cells, rounds of outer G', tuned slab tile and
  * workgroups per CU of the fused pair launch, tuned launch time (ms). */
 ltmp2_status ltmp2_batch_group(const ltmp2_batch* b, int g, int* n_fft, int* n_cells, int* rounds,

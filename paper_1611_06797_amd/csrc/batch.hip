@@ -74,6 +74,11 @@ struct ltmp2_batch {
   hipGraphExec_t exec = nullptr;
   long calls = 0;
   int num_cus = 256;
+  // optional event timing of the fused pair launches (eager evaluation only)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+  double pair_ms = 0.0;
+  long pair_n = 0;
 };
 
 namespace {
@@ -111,8 +116,34 @@ ltmp2_status fused_pair(ltmp2_batch* b, const Group& g, const Round& r, int sx, 
 }
 
 ltmp2_status pair_launch(ltmp2_batch* b, const Group& g, const Round& r, int sx, int wg) {
-  return b->prec == LTMP2_FP64 ? fused_pair<double>(b, g, r, sx, wg)
-                               : fused_pair<float>(b, g, r, sx, wg);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (b->timing && r.total > 0 && hipEventCreate(&e0) == hipSuccess &&
+      hipEventCreate(&e1) == hipSuccess)
+    (void)hipEventRecord(e0, b->stream);
+  const ltmp2_status s = b->prec == LTMP2_FP64 ? fused_pair<double>(b, g, r, sx, wg)
+                                               : fused_pair<float>(b, g, r, sx, wg);
+  if (e1) {
+    (void)hipEventRecord(e1, b->stream);
+    b->marks.push_back({e0, e1});
+  } else if (e0) {
+    (void)hipEventDestroy(e0);
+  }
+  return s;
+}
+
+void collect_batch_timing(ltmp2_batch* b) {
+  if (b->marks.empty()) return;
+  (void)hipStreamSynchronize(b->stream);
+  for (auto& m : b->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m.first, m.second) == hipSuccess) {
+      b->pair_ms += ms;
+      b->pair_n += 1;
+    }
+    (void)hipEventDestroy(m.first);
+    (void)hipEventDestroy(m.second);
+  }
+  b->marks.clear();
 }
 
 // the whole evaluation of one group (enqueued on the batch stream)
@@ -358,10 +389,10 @@ extern "C" ltmp2_status ltmp2_batch_energy(ltmp2_batch* b, double* e_direct,
   if (!b) return bfail(nullptr, LTMP2_EINVAL, "batch is NULL");
   if (b->failed) return bfail(b, LTMP2_ESTATE, "batch failed earlier: " + b->err);
   ltmp2_status s;
-  if (b->calls == 0) {
+  if (b->calls == 0 || b->timing) {
     for (Group& g : b->groups)
       if (!g.tuned && (s = tune_group(b, g))) return s;
-    if ((s = run_all(b))) return s;  // eager first evaluation
+    if ((s = run_all(b))) return s;  // eager evaluation (first call, or timed)
   } else {
     if (!b->exec) {
       if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed))
@@ -402,6 +433,39 @@ extern "C" ltmp2_status ltmp2_batch_energy(ltmp2_batch* b, double* e_direct,
   return LTMP2_OK;
 }
 
+extern "C" ltmp2_status ltmp2_batch_set_timing(ltmp2_batch* b, int on) {
+  if (!b) return LTMP2_EINVAL;
+  collect_batch_timing(b);
+  b->timing = on != 0;
+  b->pair_ms = 0.0;
+  b->pair_n = 0;
+  for (ltmp2_ctx* c : b->cells) (void)ltmp2_set_timing(c, on);
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_batch_get_timing(ltmp2_batch* b, int stage, double* ms,
+                                               long* launches) {
+  if (!b || stage < 0 || stage > 6) return LTMP2_EINVAL;
+  collect_batch_timing(b);
+  double t = 0.0;
+  long n = 0;
+  if (stage == 5) {
+    t = b->pair_ms;
+    n = b->pair_n;
+  } else {
+    for (ltmp2_ctx* c : b->cells) {
+      double tc = 0.0;
+      long nc = 0;
+      (void)ltmp2_get_timing(c, stage, &tc, &nc);
+      t += tc;
+      n += nc;
+    }
+  }
+  if (ms) *ms = t;
+  if (launches) *launches = n;
+  return LTMP2_OK;
+}
+
 extern "C" ltmp2_status ltmp2_batch_info(const ltmp2_batch* b, ltmp2_batch_stats* st) {
   if (!b || !st) return LTMP2_EINVAL;
   st->n_cells = int(b->cells.size());
@@ -434,6 +498,7 @@ extern "C" ltmp2_status ltmp2_batch_cell(const ltmp2_batch* b, int k, ltmp2_info
 extern "C" void ltmp2_batch_destroy(ltmp2_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  collect_batch_timing(b);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (ltmp2_ctx* c : b->cells) ltmp2_destroy(c);

@@ -27,7 +27,8 @@ EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_
             "ltmp2_mlp_forward", "ltmp2_mlp_grad", "ltmp2_mlp_train", "ltmp2_learned_quadrature",
             "ltmp2_mlp_last_error", "ltmp2_remez_polish", "ltmp2_batch_create",
             "ltmp2_batch_energy", "ltmp2_batch_info", "ltmp2_batch_group", "ltmp2_batch_cell",
-            "ltmp2_batch_destroy", "ltmp2_batch_last_error")
+            "ltmp2_batch_destroy", "ltmp2_batch_last_error", "ltmp2_batch_set_timing",
+            "ltmp2_batch_get_timing")
 MLP_NPARAM = 5976
 STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
 
@@ -45,6 +46,11 @@ class Info(C.Structure):
                 ("n_occ", C.c_int), ("n_vir", C.c_int), ("n_tau", C.c_int),
                 ("x_min", C.c_double), ("x_max", C.c_double), ("quad_delta", C.c_double),
                 ("device_bytes", C.c_size_t), ("quad_flags", C.c_int)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("n_cells", C.c_int), ("n_groups", C.c_int), ("graph_ready", C.c_int),
+                ("device_bytes", C.c_size_t)]
 
 
 class LTMP2Error(RuntimeError):
@@ -101,13 +107,30 @@ def load(path: str = LIB_PATH):
     lib.ltmp2_remez_polish.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, vp,
                                        vp, dp, C.POINTER(C.c_int)]
     lib.ltmp2_remez_polish.restype = C.c_int
+    lib.ltmp2_batch_create.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, C.c_char_p, vp,
+                                       C.POINTER(C.c_void_p)]
+    lib.ltmp2_batch_energy.argtypes = [vp, vp, vp]
+    lib.ltmp2_batch_info.argtypes = [vp, C.POINTER(BatchStats)]
+    lib.ltmp2_batch_group.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      dp]
+    lib.ltmp2_batch_cell.argtypes = [vp, C.c_int, C.POINTER(Info)]
+    lib.ltmp2_batch_set_timing.argtypes = [vp, C.c_int]
+    lib.ltmp2_batch_get_timing.argtypes = [vp, C.c_int, dp, C.POINTER(C.c_long)]
+    lib.ltmp2_batch_destroy.argtypes = [vp]
+    lib.ltmp2_batch_destroy.restype = None
+    lib.ltmp2_batch_last_error.argtypes = [vp]
+    lib.ltmp2_batch_last_error.restype = C.c_char_p
     lib.ltmp2_mlp_last_error.argtypes = []
     lib.ltmp2_mlp_last_error.restype = C.c_char_p
     for name in ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
                  "ltmp2_get_quadrature", "ltmp2_get_info", "ltmp2_aux_miller",
                  "ltmp2_quadrature", "ltmp2_set_timing", "ltmp2_get_timing", "ltmp2_mlp_init",
                  "ltmp2_quadrature_table", "ltmp2_mlp_dataset", "ltmp2_mlp_forward",
-                 "ltmp2_mlp_grad", "ltmp2_mlp_train", "ltmp2_learned_quadrature"):
+                 "ltmp2_mlp_grad", "ltmp2_mlp_train", "ltmp2_learned_quadrature",
+                 "ltmp2_batch_create", "ltmp2_batch_energy", "ltmp2_batch_info",
+                 "ltmp2_batch_group", "ltmp2_batch_cell", "ltmp2_batch_set_timing",
+                 "ltmp2_batch_get_timing"):
         getattr(lib, name).restype = C.c_int
     lib.ltmp2_supported_grids.restype = C.c_int
     _lib = lib
@@ -362,6 +385,118 @@ class Context:
         st = self.lib.ltmp2_energy(self._ctx, C.byref(ed), C.byref(ex), _ptr(pt), C.byref(qe))
         _check(self.lib, st, self._ctx)
         return ed.value, ex.value, pt.reshape(-1, 2), qe.value
+
+
+def _cell_arrays(miller, eps, coeff):
+    miller = np.ascontiguousarray(miller, np.int32)
+    eps = np.ascontiguousarray(eps, np.float64)
+    coeff = np.asarray(coeff)
+    if np.iscomplexobj(coeff):
+        coeff = np.stack([coeff.real, coeff.imag], axis=-1)
+    return miller, eps, np.ascontiguousarray(coeff, np.float64)
+
+
+class Batch:
+    """Many independent cells evaluated together (ltmp2_batch_* calls).
+
+    cells: sequence of dicts with keys L, n_fft, ecut, eaux, miller, eps,
+    coeff, n_occ, n_tau and optionally tau, w (a given quadrature).
+    """
+
+    def __init__(self, cells, prec=FP64, mlp_weights=None, stream=None):
+        self.lib = load()
+        n = len(cells)
+        params = (Params * n)()
+        keep = []
+        ptrs = {k: (C.c_void_p * n)() for k in ("m", "e", "c", "t", "w")}
+        any_given = False
+        for k, cell in enumerate(cells):
+            m, e, c = _cell_arrays(cell["miller"], cell["eps"], cell["coeff"])
+            t = cell.get("tau")
+            w = cell.get("w")
+            t = None if t is None else np.ascontiguousarray(t, np.float64)
+            w = None if w is None else np.ascontiguousarray(w, np.float64)
+            any_given |= t is not None
+            mode = QUAD_GIVEN if t is not None else (QUAD_LEARNED if mlp_weights else QUAD_PLAIN)
+            params[k] = Params(float(cell["L"]), int(cell["n_fft"]), float(cell["ecut"]),
+                               float(cell["eaux"]), int(m.shape[0]), int(e.shape[0]),
+                               int(cell["n_occ"]), int(cell["n_tau"]), mode, int(prec), 0)
+            keep += [m, e, c, t, w]
+            for key, a in zip("mectw", (m, e, c, t, w)):
+                ptrs[key][k] = None if a is None else a.ctypes.data
+        if stream is None:
+            stream = _current_stream()
+        self._b = C.c_void_p()
+        st = self.lib.ltmp2_batch_create(
+            n, C.cast(params, C.c_void_p), C.cast(ptrs["m"], C.c_void_p),
+            C.cast(ptrs["e"], C.c_void_p), C.cast(ptrs["c"], C.c_void_p),
+            C.cast(ptrs["t"], C.c_void_p) if any_given else None,
+            C.cast(ptrs["w"], C.c_void_p) if any_given else None,
+            mlp_weights.encode() if mlp_weights else None, C.c_void_p(stream), C.byref(self._b))
+        del keep
+        self._bcheck(st, None)
+        self.n_cells = n
+
+    def _bcheck(self, st, b):
+        if st != 0:
+            raise LTMP2Error(st, self.lib.ltmp2_batch_last_error(b).decode())
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            self.lib.ltmp2_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def energy(self):
+        """(E_d [n_cells], E_x [n_cells])."""
+        ed = np.zeros(self.n_cells)
+        ex = np.zeros(self.n_cells)
+        self._bcheck(self.lib.ltmp2_batch_energy(self._b, _ptr(ed), _ptr(ex)), self._b)
+        return ed, ex
+
+    def stats(self):
+        s = BatchStats()
+        self._bcheck(self.lib.ltmp2_batch_info(self._b, C.byref(s)), self._b)
+        return s
+
+    def group(self, g):
+        """dict of grid size, cells, rounds, slab_tile, wg_per_cu, tuned_ms of group g."""
+        v = [C.c_int() for _ in range(5)]
+        ms = C.c_double()
+        self._bcheck(self.lib.ltmp2_batch_group(self._b, int(g), *[C.byref(x) for x in v],
+                                                C.byref(ms)), self._b)
+        return dict(zip(("n_fft", "n_cells", "rounds", "slab_tile", "wg_per_cu"),
+                        (x.value for x in v)), tuned_ms=ms.value)
+
+    def set_timing(self, on=True):
+        self._bcheck(self.lib.ltmp2_batch_set_timing(self._b, int(on)), self._b)
+
+    def get_timing(self):
+        """{stage: (ms, launches)} accumulated since set_timing(True)."""
+        out = {}
+        for k, name in enumerate(STAGES):
+            ms = C.c_double()
+            n = C.c_long()
+            self._bcheck(self.lib.ltmp2_batch_get_timing(self._b, k, C.byref(ms), C.byref(n)),
+                         self._b)
+            out[name] = (ms.value, n.value)
+        return out
+
+    def cell_info(self, k):
+        info = Info()
+        self._bcheck(self.lib.ltmp2_batch_cell(self._b, int(k), C.byref(info)), self._b)
+        return info
 
 
 def _dptr(t):

@@ -53,6 +53,40 @@ C2 = CellSpec(L=16.0, n=32, ecut=7.5, eaux=5.0, n_occ=64, n_tau=8)
 C3 = CellSpec(L=20.0, n=40, ecut=7.5, eaux=5.0, n_occ=160, n_tau=10)
 
 
+def smooth_grid(m: int) -> int:
+    """Smallest integer >= m whose only prime factors are 2, 3 and 5."""
+    k = max(int(m), 1)
+    while True:
+        r = k
+        for p in (2, 3, 5):
+            while r % p == 0:
+                r //= p
+        if r == 1:
+            return k
+        k += 1
+
+
+def batch_specs(count: int = 64, seed: int = 0, L_range=(6.0, 14.0), ecut: float = 7.5,
+                eaux: float = 5.0, n_tau_range=(6, 12)) -> list:
+    """Many independent cells of uneven size (the batched workload).
+
+    L ~ U[L_range]; grid n = smallest 2,3,5-smooth integer >= ceil(2L)
+    (0.5 bohr spacing as in the larger single cells); N_occ = round(8 +
+    5 (L - 6)); N_tau ~ U{n_tau_range}; cell k's potential uses seed
+    1000 + k.  All draws come from default_rng(seed).
+    """
+    rng = np.random.default_rng(seed)
+    Ls = rng.uniform(L_range[0], L_range[1], size=count)
+    nts = rng.integers(n_tau_range[0], n_tau_range[1] + 1, size=count)
+    out = []
+    for k in range(count):
+        L = float(Ls[k])
+        out.append(CellSpec(L=L, n=smooth_grid(math.ceil(2.0 * L)), ecut=ecut, eaux=eaux,
+                            n_occ=int(round(8 + 5 * (L - 6.0))), n_tau=int(nts[k]),
+                            seed=1000 + k))
+    return out
+
+
 def orbital_miller(L: float, n: int, ecut: float) -> np.ndarray:
     """Miller indices of the orbital sphere |b m|^2 / 2 < ecut, sorted.
 

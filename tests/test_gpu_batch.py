@@ -1,0 +1,166 @@
+"""Batched evaluation of many uneven cells (ltmp2_batch_* through the C ABI).
+
+Small mixes of cells on three grids are checked against the CPU oracle at
+the same (tau, w) and against one single-cell context per cell; repeated
+calls (eager first call, graph capture, graph replay) must agree.  The
+full 64-cell workload is checked on sampled cells against the FP64
+single-cell path, which is itself held to the oracle elsewhere.
+Tolerance: N_occ micro-Hartree per cell; FP64 also 1e-9 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from synthetic import CellSpec, make_cell, batch_specs
+
+pytestmark = pytest.mark.gpu
+
+MIX = [CellSpec(L=6.0, n=12, ecut=6.0, eaux=4.0, n_occ=4, n_tau=6, seed=1000),
+       CellSpec(L=7.0, n=15, ecut=6.0, eaux=4.0, n_occ=5, n_tau=8, seed=1001),
+       CellSpec(L=7.4, n=15, ecut=6.0, eaux=4.0, n_occ=3, n_tau=7, seed=1002),
+       CellSpec(L=8.0, n=16, ecut=6.0, eaux=4.0, n_occ=6, n_tau=10, seed=1003),
+       CellSpec(L=6.5, n=15, ecut=6.0, eaux=4.0, n_occ=1, n_tau=6, seed=1004)]
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mix():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle.mp2 import Problem
+    from oracle.quadrature import minimax_laplace
+    out = []
+    for s in MIX:
+        m, e, c = make_cell(s)
+        P = Problem(s.L, s.n, s.eaux, m, e, c, s.n_occ)
+        tau, w, _ = minimax_laplace(*P.x_range(), s.n_tau)
+        ref = P.energies(tau, w)
+        out.append(dict(spec=s, m=m, e=e, c=c, tau=tau, w=w, ref=ref))
+    return out
+
+
+def _cells(items, given=True):
+    return [dict(L=it["spec"].L, n_fft=it["spec"].n, ecut=it["spec"].ecut,
+                 eaux=it["spec"].eaux, miller=it["m"], eps=it["e"], coeff=it["c"],
+                 n_occ=it["spec"].n_occ, n_tau=it["spec"].n_tau,
+                 tau=it["tau"] if given else None, w=it["w"] if given else None)
+            for it in items]
+
+
+def test_batch_fp64_matches_oracle(mix):
+    from paper_1611_06797_amd import Batch, FP64
+    _say("batch fp64: 5 cells on grids 12/15/16 vs oracle")
+    with Batch(_cells(mix), prec=FP64) as b:
+        ed, ex = b.energy()
+        st = b.stats()
+        groups = [b.group(g) for g in range(st.n_groups)]
+    assert st.n_cells == 5 and st.n_groups == 3
+    assert [g["n_fft"] for g in groups] == [12, 15, 16]
+    assert [g["n_cells"] for g in groups] == [1, 3, 1]
+    for g in groups:
+        assert g["slab_tile"] >= 1 and g["wg_per_cu"] in (1, 2, 4)
+    for k, it in enumerate(mix):
+        r = it["ref"]
+        tol = it["spec"].n_occ * 1e-6
+        assert abs(ed[k] - r["e_d_lt"]) < tol and abs(ex[k] - r["e_x_lt"]) < tol, k
+        assert abs(ed[k] - r["e_d_lt"]) <= 1e-9 * abs(r["e_d_lt"]), k
+        assert abs(ex[k] - r["e_x_lt"]) <= 1e-9 * abs(r["e_x_lt"]), k
+
+
+def test_batch_equals_single_cell_contexts(mix):
+    from paper_1611_06797_amd import Batch, Context, FP64
+    _say("batch fp64 vs one context per cell")
+    with Batch(_cells(mix), prec=FP64) as b:
+        ed, ex = b.energy()
+    for k, it in enumerate(mix):
+        s = it["spec"]
+        with Context(s.L, s.n, s.ecut, s.eaux, it["m"], it["e"], it["c"], s.n_occ, s.n_tau,
+                     tau=it["tau"], w=it["w"]) as ctx:
+            e1, x1, _, _ = ctx.energy()
+        assert abs(ed[k] - e1) <= 1e-12 * abs(e1) and abs(ex[k] - x1) <= 1e-12 * abs(x1), k
+
+
+def test_batch_graph_replay(mix):
+    from paper_1611_06797_amd import Batch, BF16X3
+    _say("batch bf16x3: eager call, capture, 3 replays")
+    with Batch(_cells(mix), prec=BF16X3) as b:
+        first = b.energy()
+        assert not b.stats().graph_ready
+        runs = [b.energy() for _ in range(4)]
+        assert b.stats().graph_ready
+    for ed, ex in runs:
+        assert np.allclose(ed, first[0], rtol=1e-13, atol=0)
+        assert np.allclose(ex, first[1], rtol=1e-13, atol=0)
+    for k, it in enumerate(mix):
+        r = it["ref"]
+        tol = it["spec"].n_occ * 1e-6
+        assert abs(first[0][k] - r["e_d_lt"]) < tol and abs(first[1][k] - r["e_x_lt"]) < tol, k
+
+
+def test_batch_library_quadrature(mix):
+    from paper_1611_06797_amd import Batch, Context, FP32
+    _say("batch fp32 with per-cell library quadrature")
+    with Batch(_cells(mix, given=False), prec=FP32) as b:
+        ed, ex = b.energy()
+        infos = [b.cell_info(k) for k in range(len(mix))]
+    for k, it in enumerate(mix):
+        s = it["spec"]
+        assert infos[k].n_tau == s.n_tau and infos[k].n_occ == s.n_occ
+        with Context(s.L, s.n, s.ecut, s.eaux, it["m"], it["e"], it["c"], s.n_occ, s.n_tau,
+                     prec=FP32) as ctx:
+            e1, x1, _, _ = ctx.energy()
+        assert abs(ed[k] - e1) < 1e-9 and abs(ex[k] - x1) < 1e-9, k
+
+
+def test_batch_rejects_mixed_precision_cells(mix):
+    import ctypes as C
+    from paper_1611_06797_amd import Batch, FP64, LTMP2Error
+    from paper_1611_06797_amd import ltmp2 as L
+    _say("batch argument validation")
+    cells = _cells(mix[:1])
+    cells[0]["n_occ"] = cells[0]["eps"].shape[0] + 1
+    with pytest.raises(LTMP2Error):
+        Batch(cells, prec=FP64)
+    lib = L.load()
+    out = C.c_void_p()
+    assert lib.ltmp2_batch_create(0, None, None, None, None, None, None, None, None,
+                                  C.byref(out)) == 1
+
+
+def test_full_batch_sampled_cells():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1611_06797_amd import Batch, Context, BF16X3, FP64
+    specs = batch_specs()
+    _say("full 64-cell batch (bf16x3, library quadrature) vs fp64 single cells, sampled")
+    data = [make_cell(s) for s in specs]
+    cells = [dict(L=s.L, n_fft=s.n, ecut=s.ecut, eaux=s.eaux, miller=m, eps=e, coeff=c,
+                  n_occ=s.n_occ, n_tau=s.n_tau) for s, (m, e, c) in zip(specs, data)]
+    with Batch(cells, prec=BF16X3) as b:
+        ed, ex = b.energy()
+        ed2, ex2 = b.energy()
+        st = b.stats()
+    assert st.n_cells == 64 and st.graph_ready
+    assert np.allclose(ed2, ed, rtol=1e-13, atol=0) and np.allclose(ex2, ex, rtol=1e-13, atol=0)
+    # one cell of each grid size, smallest and largest first
+    order = np.argsort([s.L for s in specs])
+    picks, seen = [], set()
+    for k in [order[0], order[-1]] + list(order):
+        if specs[k].n not in seen:
+            seen.add(specs[k].n)
+            picks.append(int(k))
+    for k in picks[:4]:
+        s = specs[k]
+        m, e, c = data[k]
+        _say(f"  cell {k}: L={s.L:.2f} n={s.n} n_occ={s.n_occ} n_tau={s.n_tau}")
+        with Context(s.L, s.n, s.ecut, s.eaux, m, e, c, s.n_occ, s.n_tau, prec=FP64) as ctx:
+            e1, x1, _, _ = ctx.energy()
+        tol = s.n_occ * 1e-6
+        assert abs(ed[k] - e1) < tol and abs(ex[k] - x1) < tol, k
