@@ -15,6 +15,7 @@ Prints one JSON line (rank 0).  Extra objects:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,9 +30,51 @@ PEAK_FP32 = 157.3e12     # FP32 vector and matrix, FLOP/s
 PEAK_BF16 = 2.5e15       # BF16 dense matrix, FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
 
+# Sources of the pair-transform kernel; HBM traffic figures taken with
+# rocprofv3 counters are only reported while these are unchanged.
+PAIR_SOURCES = ("fft.hpp", "transforms.hpp", "kernels_fft.hpp", "grid_kernels.hip")
+COPY_PROBE_BYTES = 1 << 30
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(ROOT, "paper_1611_06797_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(config, prec, kernel):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size),
+    or None when no summary matches the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{config}_{prec}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-json:"):
+                d = json.loads(line.split(":", 1)[1])
+                if d.get("kernel_hash") == kernel_hash():
+                    return d
+    return None
+
+
+def copy_probe():
+    """One plain copy of COPY_PROBE_BYTES (read + write) for counter scaling."""
+    import torch
+    x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    log(f"copy probe: {COPY_PROBE_BYTES} bytes read + written (kernel: elementwise mul)")
+    del x, y
 
 
 def workload(name):
@@ -225,6 +268,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--quad", default="learned", choices=["plain", "learned"])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 1 GiB copy kernel first (scale for HBM counter runs)")
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 form beside the headline form")
     args = ap.parse_args()
@@ -246,6 +291,8 @@ def main():
     m, e, c = make_cell(spec)
     log(f"cell ready ({time.time() - t:.1f}s): n_pw={m.shape[0]}")
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe()
     stream = torch.cuda.current_stream()
     t = time.time()
     prec = {"fp64": 0, "fp32": 1, "bf16x3": 2}[args.prec]
@@ -298,31 +345,11 @@ def main():
             f"dE_d {ed - ed64:.2e} dE_x {ex - ex64:.2e}")
 
     # dominant kernel stage and its roofline
-    dom = max(timing, key=lambda k: timing[k][0])
-    ms_tot, launches = timing[dom]
-    flops, byts = stage_work(info, spec.n, dom)
-    per_launch_s = ms_tot / 1000.0 / max(launches, 1)
-    if flops is not None:
-        per_launch = flops * args.steps / max(launches, 1)
-        ach = per_launch / per_launch_s
-        if dom == "pair" or dom == "w_synth":
-            peak = PEAK_FP64 if args.prec == "fp64" else PEAK_FP32
-            bound = "alu"
-        else:
-            peak = {"fp64": PEAK_FP64, "fp32": PEAK_FP32, "bf16x3": PEAK_BF16}[args.prec]
-            if dom == "w_gemm" and args.prec == "bf16x3":
-                peak = PEAK_FP32
-            bound = "mfma"
-        roof = {"bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None}
-    else:
-        per_launch = byts * args.steps / max(launches, 1)
-        ach = per_launch / per_launch_s
-        roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": ach / PEAK_HBM, "traffic": None}
-    roof["kernel"] = dom
-    roof["launches_per_step"] = launches / args.steps
-    roof["mean_launch_ms"] = 1000.0 * per_launch_s
+    roof = roofline(timing, lambda st: stage_work(info, spec.n, st), args.steps, args.prec)
+    tr = load_traffic(args.config, args.prec, roof["kernel"])
+    if tr is not None:
+        roof["traffic"] = tr["bytes_per_launch"]
+        roof["traffic_source"] = tr["source"]
 
     cpu = None
     if not args.no_cpu_baseline:

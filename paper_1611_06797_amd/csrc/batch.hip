@@ -208,7 +208,7 @@ ltmp2_status tune_group(ltmp2_batch* b, Group& g) {
   const int smax = b->prec == LTMP2_FP64 ? grid_ops<double>(g.n)->pair_sx_max(r0.kmax_max)
                                          : grid_ops<float>(g.n)->pair_sx_max(r0.kmax_max);
   std::vector<int> sxs{smax};
-  if (smax >= 4) sxs.push_back(smax / 2);
+  if (smax > 1) sxs.push_back(slab_tile_at_most(g.n, smax - 1));
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) || hipEventCreate(&e1)) return bfail(b, LTMP2_EDEVICE, "event");
   double best = 1e300;

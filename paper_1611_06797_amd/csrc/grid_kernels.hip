@@ -18,8 +18,8 @@ constexpr size_t kLdsCap = 150 * 1024;
 
 template <class T>
 int choose_sx(int nk) {
-  int sx = std::min(N, 8);
-  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) > kLdsCap) --sx;
+  int sx = slab_tile_at_most(N, 10);
+  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) > kLdsCap) sx = slab_tile_at_most(N, sx - 1);
   return sx;
 }
 
@@ -130,8 +130,9 @@ ltmp2_status wstates(const T* P, int npw, const int* wq, const signed char* wsgn
                      int nitems, double scale, cplx<T>* w, long ld, hipStream_t st) {
   const int nk = 2 * sc.kmax + 1;
   const size_t extra = sizeof(cplx<T>) * size_t(npw);
-  int sx = std::min(N, 8);
-  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) + extra > kLdsCap) --sx;
+  int sx = slab_tile_at_most(N, 10);
+  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) + extra > kLdsCap)
+    sx = slab_tile_at_most(N, sx - 1);
   return launch(k_wstates<T, N>, dim3(nitems), slab_lds_bytes<T>(N, nk, sx) + extra, st, P, npw,
                 wq, wsgn, sc, sx, scale, w, ld);
 }
@@ -166,6 +167,7 @@ struct PairMultiF {
     static ltmp2_status go(const PairCell* cells, const long* prefix, int ncells, int kmax_max,
                            int sx, int nblocks, hipStream_t st) {
       const int nk = 2 * kmax_max + 1;
+      if (sx < 1 || N % sx != 0 || sx > 10) return LTMP2_EINVAL;
       return launch(k_pair_multi<T, N, OPT>, dim3(unsigned(nblocks)), slab_lds_bytes<T>(N, nk, sx),
                     st, cells, prefix, ncells, sx);
     }

@@ -58,23 +58,68 @@ __device__ inline void fill_twiddles(cplx<T>* tw, int n) {
   }
 }
 
+// Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10).
+__host__ __device__ constexpr int slab_tile_at_most(int n, int cap) {
+  for (int d = cap < 10 ? cap : 10; d > 1; --d)
+    if (d != 7 && n % d == 0) return d;
+  return 1;
+}
+
+// In-place length-D transforms of the nc columns of a [D][nc] LDS array.
+template <class T, int S, int D>
+__device__ inline void column_fft(cplx<T>* a, int nc) {
+  for (int c = threadIdx.x; c < nc; c += kThreads) {
+    cplx<T> v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = a[k * nc + c];
+    Fft<T, S, D>::run(v);
+#pragma unroll
+    for (int k = 0; k < D; ++k) a[k * nc + c] = v[k];
+  }
+}
+
+// Slab tiles: divisors d <= 10 of the grid size (d = 1 is a no-op).
+template <class T, int S, int N>
+__device__ inline void column_fft_tile(cplx<T>* a, int d, int nc) {
+  if constexpr (N % 10 == 0) if (d == 10) return column_fft<T, S, 10>(a, nc);
+  if constexpr (N % 9 == 0) if (d == 9) return column_fft<T, S, 9>(a, nc);
+  if constexpr (N % 8 == 0) if (d == 8) return column_fft<T, S, 8>(a, nc);
+  if constexpr (N % 6 == 0) if (d == 6) return column_fft<T, S, 6>(a, nc);
+  if constexpr (N % 5 == 0) if (d == 5) return column_fft<T, S, 5>(a, nc);
+  if constexpr (N % 4 == 0) if (d == 4) return column_fft<T, S, 4>(a, nc);
+  if constexpr (N % 3 == 0) if (d == 3) return column_fft<T, S, 3>(a, nc);
+  if constexpr (N % 2 == 0) if (d == 2) return column_fft<T, S, 2>(a, nc);
+}
+
 // Forward pruned transform of NF fields.  Load(f, x, y, z) returns the
 // field value; acc[f][t] accumulates output o = threadIdx.x + t * kThreads
 // (o < nout) whose packed descriptor is gdesc[t] (pre-loaded by the caller).
+//
+// The x transform is split as N = M * sx (sx divides N): slab group x2
+// holds the planes x = x2 + M xs, xs < sx.  After the z and y passes of the
+// group, a length-sx FFT across its planes gives, for every kept (ky, kz),
+// Y_x2(q) = sum_xs f(x2 + M xs) w_sx^{q xs}; output kx then needs only
+// w_N^{kx x2} Y_x2(kx mod sx), one product per group instead of sx.
 template <class T, int S, int N, int NF, int OPT, class Load>
 __device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax, int sx,
                                       const int (&gdesc)[OPT], int nout,
                                       cplx<T> (&acc)[NF][OPT], const SlabLds<T>& L) {
-  const int nk = 2 * kmax + 1;
+  const int nk = 2 * kmax + 1, nc = nk * nk, M = N / sx;
   const int tid = threadIdx.x;
-  for (int x0 = 0; x0 < N; x0 += sx) {
+  int off[OPT], kx[OPT];
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int kxm = gdesc[t] & 0xff, kyi = (gdesc[t] >> 8) & 0xff, kzi = gdesc[t] >> 16;
+    kx[t] = kxm;
+    off[t] = ((kxm % sx) * nk + kyi) * nk + kzi;
+  }
+  for (int x2 = 0; x2 < M; ++x2) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       if (f >= nf_active) break;
       // z pass: line (xs, y)
       for (int l = tid; l < sx * N; l += kThreads) {
-        const int xs = l / N, y = l - xs * N, x = x0 + xs;
-        if (x >= N) continue;
+        const int xs = l / N, y = l - xs * N, x = x2 + M * xs;
         cplx<T> v[N];
 #pragma unroll
         for (int z = 0; z < N; ++z) v[z] = ld(f, x, y, z);
@@ -89,7 +134,6 @@ __device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax, i
       // y pass: line (xs, kz)
       for (int l = tid; l < sx * nk; l += kThreads) {
         const int xs = l / nk, kzi = l - xs * nk;
-        if (x0 + xs >= N) continue;
         cplx<T> v[N];
         const cplx<T>* src = L.t1 + (xs * nk + kzi) * (N + 1);
 #pragma unroll
@@ -102,19 +146,13 @@ __device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax, i
         }
       }
       __syncthreads();
-      // x direct DFT into the owned outputs
+      // x: length-sx FFT across the group's planes, then one product per output
+      column_fft_tile<T, S, N>(L.t2, sx, nc);
+      if (sx > 1) __syncthreads();
 #pragma unroll
       for (int t = 0; t < OPT; ++t) {
         const int o = tid + t * kThreads;
-        if (o < nout) {
-          const int kxm = gdesc[t] & 0xff, kyi = (gdesc[t] >> 8) & 0xff, kzi = gdesc[t] >> 16;
-          cplx<T> a = acc[f][t];
-          for (int xs = 0; xs < sx && x0 + xs < N; ++xs) {
-            const int e = (kxm * (x0 + xs)) % N;
-            a = cfma(L.tw[e], L.t2[(xs * nk + kyi) * nk + kzi], a);
-          }
-          acc[f][t] = a;
-        }
+        if (o < nout) acc[f][t] = cfma(L.tw[(kx[t] * x2) % N], L.t2[off[t]], acc[f][t]);
       }
       __syncthreads();
     }
@@ -124,38 +162,47 @@ __device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax, i
 // Inverse transform of NF coefficient vectors given on a sphere whose
 // entries are grouped in (ky, kz) columns: column c covers entries
 // [cstart[c], cstart[c+1]) with packed (ky + kmax) | (kz + kmax) << 8 in
-// cdesc[c] and kx values ckx[e].  Coef(f, e) returns entry e of item f;
-// Store(f, x, y, z, v) receives the synthesised grid value.  t2 must be
-// zeroed once by the caller (entries outside the columns stay zero).
+// cdesc[c] and consecutive, ascending kx values ckx[e].  Coef(f, e) returns
+// entry e of item f; Store(f, x, y, z, v) receives the synthesised grid
+// value.  t2 must be zeroed once by the caller (entries outside the columns
+// stay zero).
+//
+// The x transform uses the same split as the forward one (sx divides N,
+// group x2 = planes x2 + M xs): per column and residue q < sx,
+// Z(q) = sum_{kx = q mod sx} c(kx) w_N^{kx x2}, then a length-sx FFT over q
+// gives the group's planes.
 template <class T, int N, int NF, class Coef, class Store>
 __device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_active, int kmax,
                                       int sx, int ncol, const int* cdesc, const int* cstart,
                                       const int* ckx, const SlabLds<T>& L) {
-  const int nk = 2 * kmax + 1;
+  const int nk = 2 * kmax + 1, nc = nk * nk, M = N / sx;
   const int tid = threadIdx.x;
-  for (int x0 = 0; x0 < N; x0 += sx) {
+  for (int x2 = 0; x2 < M; ++x2) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       if (f >= nf_active) break;
-      // x stage: column sums for each slab
+      // x stage: residue sums for each column
       for (int l = tid; l < sx * ncol; l += kThreads) {
-        const int xs = l / ncol, c = l - xs * ncol, x = x0 + xs;
-        if (x >= N) continue;
+        const int q = l / ncol, c = l - q * ncol;
+        const int e0 = cstart[c], e1 = cstart[c + 1];
+        int kxm = ckx[e0] % N;
+        if (kxm < 0) kxm += N;
+        const int skip = (q - kxm % sx + sx) % sx;
+        kxm += skip;
         cplx<T> s = {T(0), T(0)};
-        const int e1 = cstart[c + 1];
-        for (int e = cstart[c]; e < e1; ++e) {
-          int kxm = ckx[e] % N;
-          if (kxm < 0) kxm += N;
-          s = cfma(cf(f, e), L.tw[(kxm * x) % N], s);
+        for (int e = e0 + skip; e < e1; e += sx) {
+          s = cfma(cf(f, e), L.tw[(kxm * x2) % N], s);
+          kxm += sx;
         }
         const int d = cdesc[c];
-        L.t2[(xs * nk + (d & 0xff)) * nk + (d >> 8)] = s;
+        L.t2[(q * nk + (d & 0xff)) * nk + (d >> 8)] = s;
       }
       __syncthreads();
+      column_fft_tile<T, 1, N>(L.t2, sx, nc);
+      if (sx > 1) __syncthreads();
       // y stage: line (xs, kz)
       for (int l = tid; l < sx * nk; l += kThreads) {
         const int xs = l / nk, kzi = l - xs * nk;
-        if (x0 + xs >= N) continue;
         cplx<T> v[N];
 #pragma unroll
         for (int y = 0; y < N; ++y) {
@@ -171,8 +218,7 @@ __device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_ac
       __syncthreads();
       // z stage: line (xs, y)
       for (int l = tid; l < sx * N; l += kThreads) {
-        const int xs = l / N, y = l - xs * N, x = x0 + xs;
-        if (x >= N) continue;
+        const int xs = l / N, y = l - xs * N, x = x2 + M * xs;
         cplx<T> v[N];
 #pragma unroll
         for (int z = 0; z < N; ++z) {

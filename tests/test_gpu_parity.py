@@ -233,3 +233,32 @@ def test_c2_full_precision_forms(c2_cell):
         ed, ex, pt, _ = res[prec]
         print(f"[c2 prec={prec}] dE_d={ed - ed0:.3e} dE_x={ex - ex0:.3e}", flush=True)
         assert abs(ed - ed0) < spec.n_occ * 1e-6 and abs(ex - ex0) < spec.n_occ * 1e-6
+
+
+def test_c3_occupied_subset_vs_oracle(torch_cuda):
+    # the large mixed-precision cell (40^3 grid, 7649 virtuals) restricted to the
+    # occupied subset I = {156, 157, 158, 159}, every precision against the
+    # oracle (stored by tests/golden/make_c3_subset.py: minutes of CPU time)
+    import json
+    import os
+    from synthetic import C3
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3_subset.json")) as f:
+        ref = json.load(f)
+    m, e, c = make_cell(C3)
+    occ = np.array(ref["occ"])
+    _say("C3 occupied subset", occ.tolist())
+    tau, w = np.array(ref["tau"]), np.array(ref["w"])
+    sel = np.concatenate([occ, np.arange(C3.n_occ, len(e))])
+    sub = CellSpec(L=C3.L, n=C3.n, ecut=C3.ecut, eaux=C3.eaux, n_occ=len(occ),
+                   n_tau=C3.n_tau, seed=C3.seed)
+    for prec in (0, 1, 2):
+        with _ctx(sub, m, e[sel], c[sel], tau=tau, w=w, prec=prec) as ctx:
+            ed, ex, pt, qe = ctx.energy()
+        dd, dx = ed - ref["e_d_lt"], ex - ref["e_x_lt"]
+        print(f"[c3-subset prec={prec}] E_d={ed:.10f} dE_d={dd:.3e} E_x={ex:.10f} dE_x={dx:.3e}",
+              flush=True)
+        assert abs(dd) < len(occ) * 1e-6 and abs(dx) < len(occ) * 1e-6
+        if prec == 0:
+            assert abs(dd) <= 1e-9 * abs(ref["e_d_lt"]) and abs(dx) <= 1e-9 * abs(ref["e_x_lt"])
+            assert np.allclose(pt[:, 0], ref["per_tau_d"], rtol=1e-9, atol=0)
+            assert np.allclose(pt[:, 1], ref["per_tau_x"], rtol=1e-9, atol=0)
