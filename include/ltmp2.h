@@ -64,7 +64,7 @@ typedef enum {
 
 typedef enum {
   LTMP2_QUAD_PLAIN = 0,   /* library computes the minimax fit               */
-  LTMP2_QUAD_LEARNED = 1, /* MLP proposal + Remez polish + certified judge  */
+  LTMP2_QUAD_LEARNED = 1, /* MLP proposal + Remez polish + certification   */
   LTMP2_QUAD_GIVEN = 2    /* caller passes tau and w                         */
 } ltmp2_quad_mode;
 
@@ -88,7 +88,7 @@ typedef struct {
 
 /* Sizes of a prepared context. */
 typedef struct {
-  int n_r;        /* n^3                                                  */
+  int n_r;        /* n_grid^3: points of the internal transform grid      */
   int n_g;        /* auxiliary set size (G and -G both counted)           */
   int n_h;        /* n_g / 2: the half set, first in the library's order  */
   int n_pw, n_occ, n_vir, n_tau;
@@ -98,6 +98,14 @@ typedef struct {
   int quad_flags;        /* LTMP2_QUAD_LEARNED only: bit 0 the polished MLP
                             proposal was certified, bit 1 the plain fit was
                             used instead, bit 2 the weight file was unusable */
+  int n_grid;            /* side of the internal transform grid: the smallest
+                            compiled size <= n_fft with n_grid >= 2 k_orb +
+                            k_aux + 1 (k_orb, k_aux: largest |Miller index| of
+                            the orbital and auxiliary spheres), else n_fft.
+                            Products of orbital-sphere functions are alias-free
+                            at the auxiliary wavevectors on it, so every energy
+                            equals the n_fft-grid value to rounding.  Grid rows
+                            of ltmp2_green are on this grid. */
 } ltmp2_info;
 
 /*
@@ -121,12 +129,12 @@ ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller, const dou
 
 /*
  * Occupied and virtual imaginary-time Green's functions at tau_itau
- * (spec G_occ / G_vir; the occupied and virtual sums of
- * Eq. dLTMP2Compact), rows [row0, row0 + nrows) of the n_r x n_r matrices
+ * (the occupied and virtual sums of Eq. dLTMP2Compact), rows [row0, row0 + nrows) of the n_r x n_r matrices
  *   G_occ(r, r') = sum_i psi_i(r) exp((e_i - mu) tau) psi_i(r')
  *   G_vir(r, r') = sum_a psi_a(r) exp(-(e_a - mu) tau) psi_a(r')
  * with mu = (e_HOMO + e_LUMO) / 2, written as doubles [nrows][n_r] to the
- * caller's device buffers (either may be NULL).  Diagnostic entry point.
+ * caller's device buffers (either may be NULL); r runs over the internal
+ * transform grid (ltmp2_info.n_grid).  Diagnostic entry point.
  */
 ltmp2_status ltmp2_green(ltmp2_ctx* ctx, int itau, int row0, int nrows, void* gocc_dev,
                          void* gvir_dev);

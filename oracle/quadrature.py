@@ -298,6 +298,6 @@ def rel_error_curve(x, tau, w):
 
 
 def max_rel_error(x_min, x_max, tau, w, ngrid=200000):
-    """Max relative error on a dense log grid (the judge of a fit)."""
+    """Max relative error on a dense log grid (the acceptance measure of a fit)."""
     x = np.exp(np.linspace(math.log(x_min), math.log(x_max), ngrid))
     return float(np.abs(rel_error_curve(x, tau, w)).max())

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libltmp2.so")
-GRIDS = (12, 15, 16, 18, 20, 24, 25, 27, 30, 32, 40)
+GRIDS = (12, 15, 16, 18, 20, 24, 25, 27, 30, 32, 36, 40)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -18,6 +18,14 @@ struct ltmp2_ctx {
 
   // sizes
   int n = 0, nr = 0, npw = 0, nst = 0, no = 0, nv = 0, ng = 0, nh = 0, ntau = 0, npairs = 0;
+  int ldbpw = 0;  // row stride of d_bpw (n_pw rounded up to a multiple of 4)
+  // split-BF16x3 operands (k-octet-blocked hi / lo, see kernels_gemm3.hpp):
+  // orbitals scaled by sqrt of the Laplace factors (per tau), overlap
+  // densities (once), virtual basis scaled by the virtual factors (per tau)
+  int kpo = 0, kpv = 0;  // occupied / virtual counts rounded up to 64
+  long ldnd3 = 0, ldb3 = 0;
+  void *d_psi3h = nullptr, *d_psi3l = nullptr, *d_nd3h = nullptr, *d_nd3l = nullptr;
+  void *d_b3h = nullptr, *d_b3l = nullptr;
   long nrp = 0;  // padded row stride of grid arrays (multiple of 64)
   int kmax_aux = 0, kmax_orb = 0, gblock = 0;
   double omega = 0, dV = 0, mu = 0, xmin = 0, xmax = 0, quad_delta = 0;
@@ -43,7 +51,7 @@ struct ltmp2_ctx {
   size_t esz = sizeof(double);
   void* d_psi = nullptr;       // [nst][nrp]
   void* d_nd = nullptr;        // [nv][nh][no] complex
-  void* d_bpw = nullptr;       // [nv][npw] real basis of virtual coefficients
+  void* d_bpw = nullptr;       // [nv][ldbpw] real basis of virtual coefficients
   void* d_chi = nullptr;       // [nrp][nrp]
   void* d_chihat = nullptr;    // [nh][nrp] complex
   double* d_pd = nullptr;      // [nh]

@@ -45,13 +45,27 @@ template <class T>
 const GridOps<T>* grid_ops(int n);
 
 // Matrix-core contractions (instantiated in registry.hip, see kernels_gemm.hpp).
+// launch_gf_chi covers the symmetric n x n block (n a multiple of 64) with
+// upper-triangular tile pairs.
 template <int MODE>
 ltmp2_status launch_gf_chi(const void* psi, long ld, int no, int nv, const double* fo,
-                           const double* fv, void* chi, long ldc, long ntiles, hipStream_t st);
+                           const double* fv, void* chi, long ldc, long n, hipStream_t st);
 template <int MODE>
 ltmp2_status launch_gemm_kmajor(const void* A, long lda, const void* B, long ldb, void* C,
                                 long ldc, int M, int N, int K, const double* sk,
                                 const double* rowscale, int rdiv, int rmod, hipStream_t st);
+
+// Split-BF16x3 path (kernels_gemm3.hpp): operand splitting into the
+// k-octet-blocked hi / lo layout, the Green's-function tiles, and the
+// general product.
+ltmp2_status launch_split3(const float* src, long lds, int K, int Kpad, int M, long ldo,
+                           const double* sk, int mode, void* hi, void* lo, long o0,
+                           hipStream_t st);
+ltmp2_status launch_chi3(const void* hi, const void* lo, long ld, int kpo, int kpv, long n,
+                         float* chi, long ldc, hipStream_t st);
+ltmp2_status launch_mm3(const void* ahi, const void* alo, long lda, long am0, const void* bhi,
+                        const void* blo, long ldb, float* C, long ldc, int M, int N, int Kpad,
+                        const double* rowscale, int rdiv, int rmod, hipStream_t st);
 
 // float -> double copy (diagnostic outputs of FP32 contexts)
 __global__ void k_widen(const float* in, double* out, long n);

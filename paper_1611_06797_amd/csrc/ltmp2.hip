@@ -279,10 +279,25 @@ ltmp2_status prepare_cell(ltmp2_ctx* c, const cplx<double>* d_coef) {
 ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
                         const double* coeff, const double* tau, const double* w) {
   const ltmp2_params& P = c->prm;
-  const int n = P.n_fft;
+  // Transform grid: the smallest compiled grid n' <= n_fft on which every
+  // product of two orbital-sphere functions is alias-free at the kept
+  // auxiliary wavevectors (n' >= 2 k_orb + k_aux + 1 per axis).  There the
+  // grid sums equal the plane-wave integrals, so the energies are those of
+  // the n_fft grid to rounding; if n_fft itself is below the bound, n_fft is
+  // used (and its aliasing is part of the model).
+  int n = P.n_fft;
+  {
+    int ko = 0;
+    for (int k = 0; k < 3 * P.n_pw; ++k) ko = std::max(ko, std::abs(int(miller[k])));
+    const double bb = 2.0 * M_PI / P.L;
+    const int ka = int(std::sqrt(double(int(std::floor(2.0 * P.eaux / (bb * bb) + 1e-9)))));
+    const int need = 2 * ko + ka + 1;
+    for (int g : supported_grids())
+      if (g >= need && g < n) n = g;
+  }
   c->n = n;
   c->nr = n * n * n;
-  c->nrp = (c->nr + 63) / 64 * 64;
+  c->nrp = (c->nr + 127) / 128 * 128;  // whole 128 x 128 Green's-function tiles
   c->npw = P.n_pw;
   c->nst = P.n_states ? P.n_states : P.n_pw;
   c->no = P.n_occ;
@@ -391,7 +406,8 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
   }
   // coefficients in column order, and the real basis of the virtual ones
   std::vector<double> coef_col(2 * size_t(c->nst) * c->npw);
-  std::vector<double> bpw(size_t(c->nv) * c->npw);
+  c->ldbpw = (c->npw + 3) / 4 * 4;  // 16-byte aligned rows
+  std::vector<double> bpw(size_t(c->nv) * c->ldbpw, 0.0);
   for (int s = 0; s < c->nst; ++s) {
     const double* cs = coeff + 2 * size_t(s) * c->npw;
     for (int e = 0; e < c->npw; ++e) {
@@ -399,7 +415,7 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
       coef_col[2 * (size_t(s) * c->npw + e) + 1] = cs[2 * order[e] + 1];
     }
     if (s >= c->no) {
-      double* row = bpw.data() + size_t(s - c->no) * c->npw;
+      double* row = bpw.data() + size_t(s - c->no) * c->ldbpw;
       row[0] = cs[2 * zero_idx];
       for (int k = 0; k < c->npw; ++k) {
         const int x = miller[3 * k], y = miller[3 * k + 1], z = miller[3 * k + 2];
@@ -459,9 +475,17 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
   c->esz = (P.prec == LTMP2_FP64) ? sizeof(double) : sizeof(float);
   const size_t es = c->esz;
   size_t fixed = es * (size_t(c->nst) * nrp + 2 * size_t(c->nv) * c->nh * c->no +
-                       size_t(c->nv) * c->npw + nrp * nrp + 2 * size_t(c->nh) * nrp) +
+                       size_t(c->nv) * c->ldbpw + nrp * nrp + 2 * size_t(c->nh) * nrp) +
                  sizeof(double) * (size_t(c->nh) + size_t(c->nh) * c->npairs) +
                  sizeof(double) * 2 * size_t(c->nst) * c->npw;
+  if (P.prec == LTMP2_BF16X3) {
+    c->kpo = (c->no + 63) / 64 * 64;
+    c->kpv = (c->nv + 63) / 64 * 64;
+    c->ldnd3 = (2L * c->nh * c->no + 127) / 128 * 128 + 128;
+    c->ldb3 = (c->npw + 127) / 128 * 128;
+    fixed += 4 * (size_t(c->kpo + c->kpv) * nrp + size_t(c->kpv) * c->ldnd3 +
+                  size_t(c->kpv) * c->ldb3);
+  }
   const size_t per_g = es * (2 * size_t(c->no) * c->npw + 2 * size_t(c->no) * nrp);
   size_t budget = size_t(8) << 30;
   if (P.workspace_cap) {
@@ -503,6 +527,18 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
       (s = dalloc(c, &c->d_xpart, size_t(c->nh) * c->npairs)) ||
       (s = dalloc(c, &c->d_scal, 2 * size_t(c->ntau) + 8)))
     return s;
+  if (P.prec == LTMP2_BF16X3) {
+    const size_t bp = 2 * size_t(c->kpo + c->kpv) * nrp, bn = 2 * size_t(c->kpv) * c->ldnd3,
+                 bb = 2 * size_t(c->kpv) * c->ldb3;
+    if ((s = dalloc_bytes(c, &c->d_psi3h, bp)) || (s = dalloc_bytes(c, &c->d_psi3l, bp)) ||
+        (s = dalloc_bytes(c, &c->d_nd3h, bn)) || (s = dalloc_bytes(c, &c->d_nd3l, bn)) ||
+        (s = dalloc_bytes(c, &c->d_b3h, bb)) || (s = dalloc_bytes(c, &c->d_b3l, bb)))
+      return s;
+    HIPCHK(c, hipMemsetAsync(c->d_nd3h, 0, bn, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_nd3l, 0, bn, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_b3h, 0, bb, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_b3l, 0, bb, c->stream));
+  }
   if (P.workspace_cap && c->bytes > P.workspace_cap)
     return fail(nullptr, LTMP2_ENOMEM, "device footprint exceeds the workspace cap");
   HIPCHK(c, hipMemsetAsync(c->d_psi, 0, es * size_t(c->nst) * nrp, c->stream));
@@ -513,6 +549,11 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
           ? prepare_cell<double>(c, reinterpret_cast<const cplx<double>*>(d_coef))
           : prepare_cell<float>(c, reinterpret_cast<const cplx<double>*>(d_coef));
   if (s) return s;
+  if (P.prec == LTMP2_BF16X3 &&
+      (s = launch_split3(static_cast<const float*>(c->d_nd), 2L * c->nh * c->no, c->nv, c->kpv,
+                         2 * c->nh * c->no, c->ldnd3, nullptr, 0, c->d_nd3h, c->d_nd3l, 0,
+                         c->stream)))
+    return fail(nullptr, s, "overlap-density split launch failed");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LTMP2_OK;
 }
@@ -531,11 +572,22 @@ ltmp2_status run_direct_t(ltmp2_ctx* c, int itau, double* chi_out) {
   const GridOps<T>* ops = grid_ops<T>(c->n);
   const double* fo = c->d_fo + size_t(itau) * c->no;
   const double* fv = c->d_fv + size_t(itau) * c->nv;
-  const long nt = c->nrp / 64;
   {
     StageTimer tm(c, 0);
-    s = launch_gf_chi<MODE>(c->d_psi, c->nrp, c->no, c->nv, fo, fv, c->d_chi, c->nrp,
-                            nt * (nt + 1) / 2, c->stream);
+    if constexpr (MODE == kBF16x3) {
+      const float* psi = static_cast<const float*>(c->d_psi);
+      s = launch_split3(psi, c->nrp, c->no, c->kpo, int(c->nrp), c->nrp, fo, 2, c->d_psi3h,
+                        c->d_psi3l, 0, c->stream);
+      if (!s)
+        s = launch_split3(psi + long(c->no) * c->nrp, c->nrp, c->nv, c->kpv, int(c->nrp), c->nrp,
+                          fv, 2, c->d_psi3h, c->d_psi3l, c->kpo / 8, c->stream);
+      if (!s)
+        s = launch_chi3(c->d_psi3h, c->d_psi3l, c->nrp, c->kpo, c->kpv, c->nrp,
+                        static_cast<float*>(c->d_chi), c->nrp, c->stream);
+    } else {
+      s = launch_gf_chi<MODE>(c->d_psi, c->nrp, c->no, c->nv, fo, fv, c->d_chi, c->nrp, c->nrp,
+                              c->stream);
+    }
   }
   if (s) return fail(c, s, "chi tile launch failed");
   {
@@ -577,9 +629,19 @@ ltmp2_status block_prepare_t(ltmp2_ctx* c, int itau, int g0, int gb) {
   // P = C Psi_v in the real basis:  C_ja = fo_j fv_a n_aj(G')
   {
     StageTimer tm(c, 3);
-    s = launch_gemm_kmajor<MODE>(static_cast<const T*>(c->d_nd) + 2L * g0 * c->no, lda, c->d_bpw,
-                                 (long)c->npw, c->d_P, (long)c->npw, M, c->npw, c->nv, fv, fo, 2,
-                                 c->no, c->stream);
+    if constexpr (MODE == kBF16x3) {
+      // C_ja Psi_v = fo_j sum_a n_aj (fv_a B_a): the virtual factors go into B
+      s = launch_split3(static_cast<const float*>(c->d_bpw), c->ldbpw, c->nv, c->kpv, c->npw,
+                        c->ldb3, fv, 1, c->d_b3h, c->d_b3l, 0, c->stream);
+      if (!s)
+        s = launch_mm3(c->d_nd3h, c->d_nd3l, c->ldnd3, 2L * g0 * c->no, c->d_b3h, c->d_b3l,
+                       c->ldb3, static_cast<float*>(c->d_P), c->npw, M, c->npw, c->kpv, fo, 2,
+                       c->no, c->stream);
+    } else {
+      s = launch_gemm_kmajor<MODE>(static_cast<const T*>(c->d_nd) + 2L * g0 * c->no, lda,
+                                   c->d_bpw, (long)c->ldbpw, c->d_P, (long)c->npw, M, c->npw,
+                                   c->nv, fv, fo, 2, c->no, c->stream);
+    }
   }
   if (s) return fail(c, s, "transformed-state GEMM launch failed");
   {
@@ -613,7 +675,8 @@ ltmp2_status reduce_x(ltmp2_ctx* c, int itau, int g_first, int g_count) {
 ltmp2_status block_prepare(ltmp2_ctx* c, int itau, int g0, int gb) {
   switch (c->prm.prec) {
     case LTMP2_FP64: return block_prepare_t<double, kF64>(c, itau, g0, gb);
-    default: return block_prepare_t<float, kF32>(c, itau, g0, gb);
+    case LTMP2_FP32: return block_prepare_t<float, kF32>(c, itau, g0, gb);
+    default: return block_prepare_t<float, kBF16x3>(c, itau, g0, gb);
   }
 }
 
@@ -799,6 +862,7 @@ extern "C" ltmp2_status ltmp2_get_info(const ltmp2_ctx* c, ltmp2_info* info) {
   info->quad_delta = c->quad_delta;
   info->device_bytes = c->bytes;
   info->quad_flags = c->quad_flags;
+  info->n_grid = c->n;
   return LTMP2_OK;
 }
 

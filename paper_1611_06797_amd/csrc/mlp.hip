@@ -1,5 +1,5 @@
 // Learned Laplace quadrature: a small MLP proposes the minimax exponents and
-// weights, a few Remez steps polish them, and the plain fit is both the judge
+// weights, a few Remez steps polish them, and the plain fit is both the arbiter
 // (certification by equioscillation) and the fallback.
 //
 // Network: 3 -> 64 (tanh) -> 64 (tanh) -> 24, FP32.

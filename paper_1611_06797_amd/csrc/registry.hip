@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dispatch.h"
+#include "kernels_gemm3.hpp"
 #include "kernels_gemm.hpp"
 
 #ifndef LTMP2_GRID_LIST
@@ -54,9 +55,11 @@ std::vector<int> supported_grids() {
 
 template <int MODE>
 ltmp2_status launch_gf_chi(const void* psi, long ld, int no, int nv, const double* fo,
-                           const double* fv, void* chi, long ldc, long ntiles, hipStream_t st) {
+                           const double* fv, void* chi, long ldc, long n, hipStream_t st) {
   using T = typename Mma<MODE>::T;
-  hipLaunchKernelGGL(k_gf_chi<MODE>, dim3(unsigned(ntiles)), dim3(256), 0, st,
+  if (n % 64 != 0) return LTMP2_EINVAL;
+  const long t = n / 64;
+  hipLaunchKernelGGL(k_gf_chi<MODE>, dim3(unsigned(t * (t + 1) / 2)), dim3(256), 0, st,
                      static_cast<const T*>(psi), ld, no, nv, fo, fv, static_cast<T*>(chi), ldc);
   return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
 }
@@ -73,6 +76,44 @@ ltmp2_status launch_gemm_kmajor(const void* A, long lda, const void* B, long ldb
   return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
 }
 
+ltmp2_status launch_split3(const float* src, long lds, int K, int Kpad, int M, long ldo,
+                           const double* sk, int mode, void* hi, void* lo, long o0,
+                           hipStream_t st) {
+  if (Kpad % 64 != 0 || K > Kpad || M > ldo) return LTMP2_EINVAL;
+  const long items = long(Kpad / 8) * M;
+  if (items == 0) return LTMP2_OK;
+  hipLaunchKernelGGL(k_split3, dim3(unsigned((items + 255) / 256)), dim3(256), 0, st, src, lds, K,
+                     Kpad, M, ldo, sk, mode, static_cast<__bf16*>(hi), static_cast<__bf16*>(lo),
+                     o0);
+  return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
+}
+
+ltmp2_status launch_chi3(const void* hi, const void* lo, long ld, int kpo, int kpv, long n,
+                         float* chi, long ldc, hipStream_t st) {
+  if (n % 128 != 0 || ld < n || kpo % 64 != 0 || kpv % 64 != 0) return LTMP2_EINVAL;
+  const int t = int(n / 128), ts = (t + 7) / 8;
+  const long nsuper = long(ts) * (ts + 1) / 2;
+  const long blocks = (nsuper + 7) / 8 * 512;
+  Op3 op{static_cast<const __bf16*>(hi), static_cast<const __bf16*>(lo), ld};
+  hipLaunchKernelGGL(k_chi3, dim3(unsigned(blocks)), dim3(256), 0, st, op, kpo, kpv, t, chi, ldc);
+  return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
+}
+
+ltmp2_status launch_mm3(const void* ahi, const void* alo, long lda, long am0, const void* bhi,
+                        const void* blo, long ldb, float* C, long ldc, int M, int N, int Kpad,
+                        const double* rowscale, int rdiv, int rmod, hipStream_t st) {
+  if (M <= 0 || N <= 0) return LTMP2_OK;
+  if (Kpad % 64 != 0 || am0 + (M + 127) / 128 * 128 > lda || (N + 127) / 128 * 128 > ldb)
+    return LTMP2_EINVAL;
+  const long total = long((M + 127) / 128) * ((N + 127) / 128);
+  const long blocks = (total + 7) / 8 * 8;
+  Op3 a{static_cast<const __bf16*>(ahi), static_cast<const __bf16*>(alo), lda};
+  Op3 b{static_cast<const __bf16*>(bhi), static_cast<const __bf16*>(blo), ldb};
+  hipLaunchKernelGGL(k_mm3, dim3(unsigned(blocks)), dim3(256), 0, st, a, am0, b, C, ldc, M, N,
+                     Kpad, rowscale, rdiv, rmod);
+  return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
+}
+
 template ltmp2_status launch_gf_chi<kF64>(const void*, long, int, int, const double*, const double*,
                                           void*, long, long, hipStream_t);
 template ltmp2_status launch_gf_chi<kF32>(const void*, long, int, int, const double*, const double*,
@@ -85,6 +126,9 @@ template ltmp2_status launch_gemm_kmajor<kF64>(const void*, long, const void*, l
 template ltmp2_status launch_gemm_kmajor<kF32>(const void*, long, const void*, long, void*, long,
                                                int, int, int, const double*, const double*, int,
                                                int, hipStream_t);
+template ltmp2_status launch_gemm_kmajor<kBF16x3>(const void*, long, const void*, long, void*,
+                                                  long, int, int, int, const double*,
+                                                  const double*, int, int, hipStream_t);
 
 __global__ void k_widen(const float* in, double* out, long n) {
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;

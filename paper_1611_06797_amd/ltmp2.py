@@ -45,7 +45,7 @@ class Info(C.Structure):
     _fields_ = [("n_r", C.c_int), ("n_g", C.c_int), ("n_h", C.c_int), ("n_pw", C.c_int),
                 ("n_occ", C.c_int), ("n_vir", C.c_int), ("n_tau", C.c_int),
                 ("x_min", C.c_double), ("x_max", C.c_double), ("quad_delta", C.c_double),
-                ("device_bytes", C.c_size_t), ("quad_flags", C.c_int)]
+                ("device_bytes", C.c_size_t), ("quad_flags", C.c_int), ("n_grid", C.c_int)]
 
 
 class BatchStats(C.Structure):

@@ -1,6 +1,6 @@
 """Batched evaluation of many uneven cells (ltmp2_batch_* through the C ABI).
 
-Small mixes of cells on three grids are checked against the CPU oracle at
+Small mixes of cells on several grids are checked against the CPU oracle at
 the same (tau, w) and against one single-cell context per cell; repeated
 calls (eager first call, graph capture, graph replay) must agree.  The
 full 64-cell workload is checked on sampled cells against the FP64
@@ -20,7 +20,8 @@ MIX = [CellSpec(L=6.0, n=12, ecut=6.0, eaux=4.0, n_occ=4, n_tau=6, seed=1000),
        CellSpec(L=7.0, n=15, ecut=6.0, eaux=4.0, n_occ=5, n_tau=8, seed=1001),
        CellSpec(L=7.4, n=15, ecut=6.0, eaux=4.0, n_occ=3, n_tau=7, seed=1002),
        CellSpec(L=8.0, n=16, ecut=6.0, eaux=4.0, n_occ=6, n_tau=10, seed=1003),
-       CellSpec(L=6.5, n=15, ecut=6.0, eaux=4.0, n_occ=1, n_tau=6, seed=1004)]
+       CellSpec(L=6.5, n=15, ecut=6.0, eaux=4.0, n_occ=1, n_tau=6, seed=1004),
+       CellSpec(L=10.0, n=20, ecut=6.0, eaux=4.0, n_occ=5, n_tau=7, seed=1005)]
 
 
 def _say(*a):
@@ -55,14 +56,17 @@ def _cells(items, given=True):
 
 def test_batch_fp64_matches_oracle(mix):
     from paper_1611_06797_amd import Batch, FP64
-    _say("batch fp64: 5 cells on grids 12/15/16 vs oracle")
+    _say("batch fp64: 6 cells on caller grids 12/15/16/20 vs oracle")
     with Batch(_cells(mix), prec=FP64) as b:
         ed, ex = b.energy()
         st = b.stats()
         groups = [b.group(g) for g in range(st.n_groups)]
-    assert st.n_cells == 5 and st.n_groups == 3
-    assert [g["n_fft"] for g in groups] == [12, 15, 16]
-    assert [g["n_cells"] for g in groups] == [1, 3, 1]
+        grids = [b.cell_info(k).n_grid for k in range(len(mix))]
+    # cells are grouped by their internal transform grid (alias-free size)
+    assert st.n_cells == 6 and st.n_groups == 2
+    assert grids == [12, 12, 12, 12, 12, 15]
+    assert [g["n_fft"] for g in groups] == [12, 15]
+    assert [g["n_cells"] for g in groups] == [5, 1]
     for g in groups:
         assert g["slab_tile"] >= 1 and g["wg_per_cu"] in (1, 2, 4)
     for k, it in enumerate(mix):

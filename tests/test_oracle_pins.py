@@ -78,7 +78,7 @@ def test_brute_four_point_per_tau(tiny):
 
 
 def test_chi_trace_and_fock_factorisation(tiny):
-    # spec direct route and the paper's transformed-state exchange route
+    # Green's-function direct route and the paper's transformed-state exchange route
     # reproduce the per-tau Laplace terms exactly
     s, m, e, c, P = tiny
     tau = np.array([0.5, 2.5])

@@ -56,7 +56,7 @@ def test_scale_covariance():
 
 def test_laplace_integral_check():
     # int_0^inf exp(-x tau) dtau = 1/x (Eq. SCHLT): the quadrature reproduces
-    # 1/x within delta on random x of the interval, and the dense-grid judge
+    # 1/x within delta on random x of the interval, and the dense-grid error measure
     # agrees with the certified delta
     tau, w, d = minimax_laplace(0.122, 16.2, 8)
     x = np.random.default_rng(0).uniform(0.122, 16.2, 1000)
