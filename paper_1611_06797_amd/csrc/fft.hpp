@@ -33,6 +33,16 @@ template <class T>
 LT_HD cplx<T> csub(cplx<T> a, cplx<T> b) {
   return {a.x - b.x, a.y - b.y};
 }
+// a * w for a twiddle w known at compile time after unrolling: the quarter
+// turns (+-1, +-i) fold into sign changes and swaps.
+template <class T>
+LT_HD cplx<T> cmul_tw(cplx<T> a, cplx<T> w) {
+  if (w.y == T(0) && w.x == T(1)) return a;
+  if (w.y == T(0) && w.x == T(-1)) return {-a.x, -a.y};
+  if (w.x == T(0) && w.y == T(1)) return {-a.y, a.x};
+  if (w.x == T(0) && w.y == T(-1)) return {a.y, -a.x};
+  return cmul(a, w);
+}
 template <class T>
 LT_HD cplx<T> cfma(cplx<T> a, cplx<T> b, cplx<T> acc) {
   return {acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x};
@@ -193,7 +203,7 @@ struct Fft {
           if (r * k == 0) {
             t[r] = y[r][k];
           } else {
-            t[r] = cmul(y[r][k], twiddle<T, S>(long(r) * k, N));
+            t[r] = cmul_tw(y[r][k], twiddle<T, S>(long(r) * k, N));
           }
         }
         Dft<T, S, R>::run(t);

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kThreads) void k_orbitals(const cplx<double>* __res
   extern __shared__ __align__(16) char smem[];
   const int nk = 2 * sc.kmax + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
-  fill_twiddles<T, 1>(L.tw, N);
+  fill_twiddles<T, 1, N>(L.tw);
   for (int e = threadIdx.x; e < sx * nk * nk; e += kThreads) L.t2[e] = {T(0), T(0)};
   __syncthreads();
   const long p = blockIdx.x;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kThreads) void k_overlap(const T* __restrict__ psi,
   extern __shared__ __align__(16) char smem[];
   const int nk = 2 * kmax + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
-  fill_twiddles<T, -1>(L.tw, N);
+  fill_twiddles<T, -1, N>(L.tw);
   const int j0 = blockIdx.x * NF;
   const int a = blockIdx.y;
   const int nf = min(NF, nocc - j0);
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_chi_rows(const T* __restrict__ chi
   extern __shared__ __align__(16) char smem[];
   const int nk = 2 * kmax + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
-  fill_twiddles<T, 1>(L.tw, N);
+  fill_twiddles<T, 1, N>(L.tw);
   const int r0 = blockIdx.x * NF;
   const int nf = min(NF, nr - r0);
   const T* row = chi + long(r0) * ld;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict
   __shared__ double red[kThreads / 64];
   const int nk = 2 * kmax + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
-  fill_twiddles<T, -1>(L.tw, N);
+  fill_twiddles<T, -1, N>(L.tw);
   const int g = blockIdx.x;
   const cplx<T>* col = chihat + long(g) * ld;
   int gd[OPT];
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, i
   extern __shared__ __align__(16) char smem[];
   const int nk = 2 * sc.kmax + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
-  fill_twiddles<T, 1>(L.tw, N);
+  fill_twiddles<T, 1, N>(L.tw);
   for (int e = threadIdx.x; e < sx * nk * nk; e += kThreads) L.t2[e] = {T(0), T(0)};
   __syncthreads();
   const long item = blockIdx.x;
@@ -243,7 +243,7 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
                                  double* red) {
   const int nk = 2 * pc.kmax + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
-  fill_twiddles<T, -1>(L.tw, N);
+  fill_twiddles<T, -1, N>(L.tw);
   const int i = pc.pairs[p] & 0xffff, j = pc.pairs[p] >> 16;
   const T* psi = static_cast<const T*>(pc.psi);
   const cplx<T>* w = static_cast<const cplx<T>*>(pc.w);

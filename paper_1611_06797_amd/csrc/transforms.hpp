@@ -14,6 +14,8 @@
 //   per slab group: direct DFT along x from the sphere's (ky, kz) columns,
 //   FFT along y, FFT along z, write the slab.
 #pragma once
+#include <utility>
+
 #include "fft.hpp"
 
 namespace ltmp2 {
@@ -49,13 +51,18 @@ __device__ inline SlabLds<T> slab_lds(void* base, int n, int nk, int sx) {
   return s;
 }
 
-// exp(S 2 pi i e / n) for e = 0..n-1 into shared memory
-template <class T, int S>
-__device__ inline void fill_twiddles(cplx<T>* tw, int n) {
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    cs v = unit_root(e, n);
-    tw[e] = {T(v.c), T(S * v.s)};
-  }
+// exp(S 2 pi i e / N), e = 0..N-1, as a compile-time table in constant memory.
+template <class T, int S, int N, class Seq = std::make_integer_sequence<int, N>>
+struct TwiddleTable;
+template <class T, int S, int N, int... E>
+struct TwiddleTable<T, S, N, std::integer_sequence<int, E...>> {
+  static constexpr cplx<T> v[N] = {twiddle<T, S>(E, N)...};
+};
+
+// exp(S 2 pi i e / N) for e = 0..N-1 into shared memory
+template <class T, int S, int N>
+__device__ inline void fill_twiddles(cplx<T>* tw) {
+  for (int e = threadIdx.x; e < N; e += blockDim.x) tw[e] = TwiddleTable<T, S, N>::v[e];
 }
 
 // Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10).
