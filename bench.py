@@ -32,7 +32,7 @@ PEAK_HBM = 8.0e12        # bytes/s
 
 # Sources of the pair-transform kernel; HBM traffic figures taken with
 # rocprofv3 counters are only reported while these are unchanged.
-PAIR_SOURCES = ("fft.hpp", "transforms.hpp", "kernels_fft.hpp", "grid_kernels.hip")
+PAIR_SOURCES = ("fft.hpp", "transforms.hpp", "kernels_fft.hpp", "grid_kernels.hip", "ltmp2.hip")
 COPY_PROBE_BYTES = 1 << 30
 
 

@@ -58,6 +58,7 @@ struct ltmp2_ctx {
   void* d_P = nullptr;         // [gblock * no * 2][npw]
   void* d_w = nullptr;         // [gblock * no][nrp] complex
   double* d_xpart = nullptr;   // [nh][npairs]
+  double* d_xrow = nullptr;    // [nh] v(G') times the row sums of d_xpart
   double* d_scal = nullptr;    // [2 * ntau + 8] device scalars
 
   std::vector<void*> owned;

@@ -74,7 +74,8 @@ __global__ void k_widen(const float* in, double* out, long n);
 //   E_d(tau) = -4 sum_{g in H} pd[g]        (pd includes v(G'); G' and -G')
 __global__ void k_reduce_direct(const double* pd, int nh, double* out);
 //   E_x(tau) = 2 sum_{g in range} v[g] sum_p xpart[g][p]
-__global__ void k_reduce_exchange(const double* xpart, int g0, int gcount, int npairs,
-                                  const double* v, double* out);
+__global__ void k_reduce_xrows(const double* xpart, int g0, int npairs, const double* v,
+                               double* xrow);
+__global__ void k_reduce_exchange(const double* xrow, int g0, int gcount, double* out);
 
 }  // namespace ltmp2

@@ -17,8 +17,8 @@ constexpr int N = LTMP2_N;
 constexpr size_t kLdsCap = 150 * 1024;
 
 template <class T>
-int choose_sx(int nk) {
-  int sx = slab_tile_at_most(N, 10);
+int choose_sx(int nk, int cap = 10) {
+  int sx = slab_tile_at_most(N, cap);
   while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) > kLdsCap) sx = slab_tile_at_most(N, sx - 1);
   return sx;
 }
@@ -39,13 +39,24 @@ bool ensure_lds(const void* kern, size_t lds) {
 }
 
 template <class K>
-ltmp2_status launch(K kern, dim3 grid, size_t lds, hipStream_t st, auto... args) {
+ltmp2_status launch_nt(K kern, dim3 grid, int nt, size_t lds, hipStream_t st, auto... args) {
   if (lds > kLdsCap) return LTMP2_EINVAL;
   if (grid.x == 0 || grid.y == 0) return LTMP2_OK;
   if (!ensure_lds(reinterpret_cast<const void*>(kern), lds)) return LTMP2_EDEVICE;
-  hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, args...);
+  hipLaunchKernelGGL(kern, grid, dim3(nt), lds, st, args...);
   return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
 }
+
+template <class K>
+ltmp2_status launch(K kern, dim3 grid, size_t lds, hipStream_t st, auto... args) {
+  return launch_nt(kern, grid, kThreads, lds, st, args...);
+}
+
+// FP32 pair transforms with more than 9 outputs per thread run 512-thread
+// workgroups with at most 9 each: the accumulators of 17 per thread would
+// leave room for only one wave per SIMD.  (FP64 registers do not fit two
+// 512-thread waves per SIMD; FP64 keeps 256 threads.)
+constexpr int kWideNT = 512, kWideOpt = 9;
 
 template <template <int> class F>
 ltmp2_status by_opt(int nout, auto&&... a) {
@@ -156,6 +167,16 @@ template <class T>
 ltmp2_status pair(const T* psi, long ld, const cplx<T>* w, int no, const int* pairs, int npairs,
                   int gb, const int* gdesc, int ng, const double* v, int kmax, double dV2,
                   double* xpart, hipStream_t st) {
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (ng > 9 * kThreads) {
+      if (ng > kWideOpt * kWideNT) return LTMP2_EINVAL;
+      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk, 12);
+      PairCell pc{psi, w, pairs, gdesc, v, xpart, ld, no, npairs, gb, ng, kmax, dV2};
+      const long total = long(npairs) * gb;
+      return launch_nt(k_pair<T, N, kWideOpt, kWideNT>, dim3(unsigned((total + 7) / 8 * 8)),
+                       kWideNT, slab_lds_bytes<T>(N, nk, sx), st, pc, sx);
+    }
+  }
   return by_opt<PairF<T>::template F>(ng, psi, ld, w, no, pairs, npairs, gb, gdesc, ng, v, kmax,
                                       dV2, xpart, st);
 }
@@ -176,6 +197,14 @@ struct PairMultiF {
 template <class T>
 ltmp2_status pair_multi(const PairCell* cells, const long* prefix, int ncells, int ng_max,
                         int kmax_max, int sx, int nblocks, hipStream_t st) {
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (ng_max > 9 * kThreads) {
+      if (ng_max > kWideOpt * kWideNT || sx < 1 || N % sx != 0 || sx > 12) return LTMP2_EINVAL;
+      return launch_nt(k_pair_multi<T, N, kWideOpt, kWideNT>, dim3(unsigned(nblocks)), kWideNT,
+                       slab_lds_bytes<T>(N, 2 * kmax_max + 1, sx), st, cells, prefix, ncells,
+                       sx);
+    }
+  }
   return by_opt<PairMultiF<T>::template F>(ng_max, cells, prefix, ncells, kmax_max, sx, nblocks,
                                            st);
 }

@@ -238,7 +238,7 @@ struct PairCell {
   double dV2;
 };
 
-template <class T, int N, int OPT>
+template <class T, int N, int OPT, int NT = kThreads>
 __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void* smem,
                                  double* red) {
   const int nk = 2 * pc.kmax + 1;
@@ -255,7 +255,7 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
   cplx<T> acc[2][OPT];
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
-    const int o = threadIdx.x + t * kThreads;
+    const int o = threadIdx.x + t * NT;
     gd[t] = (o < pc.ng) ? pc.gdesc[o] : 0;
     acc[0][t] = {T(0), T(0)};
     acc[1][t] = {T(0), T(0)};
@@ -267,11 +267,11 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
     const cplx<T> b = (f == 0) ? wj[r] : wi[r];
     return cplx<T>{a * b.x, a * b.y};
   };
-  forward_pruned<T, -1, N, 2, OPT>(ld_, (i == j) ? 1 : 2, pc.kmax, sx, gd, pc.ng, acc, L);
+  forward_pruned<T, -1, N, 2, OPT, NT>(ld_, (i == j) ? 1 : 2, pc.kmax, sx, gd, pc.ng, acc, L);
   double s = 0.0;
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
-    const int o = threadIdx.x + t * kThreads;
+    const int o = threadIdx.x + t * NT;
     if (o < pc.ng) {
       const double ar = acc[0][t].x, ai = acc[0][t].y;
       if (i == j) {
@@ -287,30 +287,31 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
 }
 
 // One cell: workgroups are dispatched round-robin over the 8 XCDs; each XCD
-// gets a contiguous range of the (G', pair) list, pairs in i-major order, so
-// the workgroups resident on one XCD share (G', i) and psi_i, w_i stay in L2.
-template <class T, int N, int OPT>
-__global__ __launch_bounds__(kThreads) void k_pair(PairCell pc, int sx) {
+// gets a contiguous range of the (G', pair) list, whose pairs come in 8 x 8
+// blocks of (i, j), so the workgroups resident on one XCD share a handful of
+// psi_i and w_j^{(G')} in that XCD's L2.
+template <class T, int N, int OPT, int NT = kThreads>
+__global__ __launch_bounds__(NT) void k_pair(PairCell pc, int sx) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ double red[kThreads / 64];
+  __shared__ double red[NT / 64];
   const long total = long(pc.npairs) * pc.gb;
   const long per_xcd = (total + 7) / 8;
   const long t = long(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= total) return;
   const int gl = int(t / pc.npairs);
-  pair_item<T, N, OPT>(pc, gl, int(t - long(gl) * pc.npairs), sx, smem, red);
+  pair_item<T, N, OPT, NT>(pc, gl, int(t - long(gl) * pc.npairs), sx, smem, red);
 }
 
 // Several cells of the same grid in one persistent launch: the work list is
 // the concatenation of every cell's (G', pair) items (prefix[c] = first item
 // of cell c); each XCD owns a contiguous range and its workgroups stride
 // through it, so every workgroup exits after a bounded number of items.
-template <class T, int N, int OPT>
-__global__ __launch_bounds__(kThreads) void k_pair_multi(const PairCell* __restrict__ cells,
+template <class T, int N, int OPT, int NT = kThreads>
+__global__ __launch_bounds__(NT) void k_pair_multi(const PairCell* __restrict__ cells,
                                                          const long* __restrict__ prefix,
                                                          int ncells, int sx) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ double red[kThreads / 64];
+  __shared__ double red[NT / 64];
   const long total = prefix[ncells];
   const long per_xcd = (total + 7) / 8;
   const long stride = gridDim.x / 8;
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_multi(const PairCell* __restr
     const PairCell pc = cells[lo];
     const long u = t - prefix[lo];
     const int gl = int(u / pc.npairs);
-    pair_item<T, N, OPT>(pc, gl, int(u - long(gl) * pc.npairs), sx, smem, red);
+    pair_item<T, N, OPT, NT>(pc, gl, int(u - long(gl) * pc.npairs), sx, smem, red);
     __syncthreads();
   }
 }

@@ -426,9 +426,16 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
       }
     }
   }
+  // pairs i <= j in 8 x 8 blocks of (i, j): the workgroups resident on one
+  // XCD take consecutive items, and a block touches 16 orbitals and 16
+  // transformed states, which stay in that XCD's L2
   std::vector<int> pairs;
-  for (int i = 0; i < c->no; ++i)
-    for (int j = i; j < c->no; ++j) pairs.push_back(i | (j << 16));
+  constexpr int kPairBlock = 8;
+  for (int bi = 0; bi < c->no; bi += kPairBlock)
+    for (int bj = bi; bj < c->no; bj += kPairBlock)
+      for (int i = bi; i < std::min(bi + kPairBlock, c->no); ++i)
+        for (int j = std::max(i, bj); j < std::min(bj + kPairBlock, c->no); ++j)
+          pairs.push_back(i | (j << 16));
 
   // quadrature
   c->tau.resize(c->ntau);
@@ -525,6 +532,7 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
        (s = dalloc_bytes(c, &c->d_P, es * 2 * size_t(c->gblock) * c->no * c->npw))) ||
       (c->own_scratch && (s = dalloc_bytes(c, &c->d_w, es * 2 * size_t(c->gblock) * c->no * nrp))) ||
       (s = dalloc(c, &c->d_xpart, size_t(c->nh) * c->npairs)) ||
+      (s = dalloc(c, &c->d_xrow, size_t(c->nh))) ||
       (s = dalloc(c, &c->d_scal, 2 * size_t(c->ntau) + 8)))
     return s;
   if (P.prec == LTMP2_BF16X3) {
@@ -667,8 +675,11 @@ ltmp2_status block_pair_t(ltmp2_ctx* c, int g0, int gb) {
 
 ltmp2_status reduce_x(ltmp2_ctx* c, int itau, int g_first, int g_count) {
   StageTimer tm(c, 6);
-  hipLaunchKernelGGL(k_reduce_exchange, dim3(1), dim3(256), 0, c->stream, c->d_xpart, g_first,
-                     g_count, c->npairs, c->d_v, c->d_scal + 2 * itau + 1);
+  if (g_count <= 0) return LTMP2_OK;
+  hipLaunchKernelGGL(k_reduce_xrows, dim3(g_count), dim3(256), 0, c->stream, c->d_xpart, g_first,
+                     c->npairs, c->d_v, c->d_xrow);
+  hipLaunchKernelGGL(k_reduce_exchange, dim3(1), dim3(256), 0, c->stream, c->d_xrow, g_first,
+                     g_count, c->d_scal + 2 * itau + 1);
   return check_launch(c, "k_reduce_exchange");
 }
 

@@ -143,16 +143,22 @@ __global__ void k_reduce_direct(const double* pd, int nh, double* out) {
   if (threadIdx.x == 0) out[0] = -4.0 * s;
 }
 
-__global__ void k_reduce_exchange(const double* xpart, int g0, int gcount, int npairs,
-                                  const double* v, double* out) {
+// one block per G': xrow[g] = v(G') sum_p xpart[g][p] (fixed-order block sum)
+__global__ void k_reduce_xrows(const double* xpart, int g0, int npairs, const double* v,
+                               double* xrow) {
+  __shared__ double red[4];
+  const int g = g0 + blockIdx.x;
+  const double* row = xpart + size_t(g) * npairs;
+  double s = 0.0;
+  for (int p = threadIdx.x; p < npairs; p += blockDim.x) s += row[p];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) xrow[g] = v[g] * s;
+}
+
+__global__ void k_reduce_exchange(const double* xrow, int g0, int gcount, double* out) {
   __shared__ double red[4];
   double s = 0.0;
-  for (int g = g0 + threadIdx.x; g < g0 + gcount; g += blockDim.x) {
-    const double* row = xpart + size_t(g) * npairs;
-    double r = 0.0;
-    for (int p = 0; p < npairs; ++p) r += row[p];
-    s += v[g] * r;
-  }
+  for (int g = g0 + threadIdx.x; g < g0 + gcount; g += blockDim.x) s += xrow[g];
   s = block_sum(s, red);
   if (threadIdx.x == 0) out[0] = 2.0 * s;
 }

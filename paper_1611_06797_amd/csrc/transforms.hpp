@@ -30,23 +30,27 @@ __host__ __device__ inline int pack_g(int kxm, int kyi, int kzi) {
   return kxm | (kyi << 8) | (kzi << 16);
 }
 
+// Row length of the z-pass buffer: even grids get one pad element against
+// shared-memory bank conflicts, odd ones need none.
+__host__ __device__ constexpr int slab_row(int n) { return n + (n % 2 == 0 ? 1 : 0); }
+
 template <class T>
 struct SlabLds {
-  cplx<T>* t1;  // [SX][nk][n + 1]
+  cplx<T>* t1;  // [SX][nk][slab_row(n)]
   cplx<T>* t2;  // [SX][nk][nk]
   cplx<T>* tw;  // [n]
 };
 
 template <class T>
 __host__ __device__ inline size_t slab_lds_bytes(int n, int nk, int sx) {
-  return sizeof(cplx<T>) * (size_t(sx) * nk * (n + 1) + size_t(sx) * nk * nk + n);
+  return sizeof(cplx<T>) * (size_t(sx) * nk * slab_row(n) + size_t(sx) * nk * nk + n);
 }
 
 template <class T>
 __device__ inline SlabLds<T> slab_lds(void* base, int n, int nk, int sx) {
   SlabLds<T> s;
   s.t1 = reinterpret_cast<cplx<T>*>(base);
-  s.t2 = s.t1 + size_t(sx) * nk * (n + 1);
+  s.t2 = s.t1 + size_t(sx) * nk * slab_row(n);
   s.tw = s.t2 + size_t(sx) * nk * nk;
   return s;
 }
@@ -65,17 +69,17 @@ __device__ inline void fill_twiddles(cplx<T>* tw) {
   for (int e = threadIdx.x; e < N; e += blockDim.x) tw[e] = TwiddleTable<T, S, N>::v[e];
 }
 
-// Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10).
+// Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10, 12).
 __host__ __device__ constexpr int slab_tile_at_most(int n, int cap) {
-  for (int d = cap < 10 ? cap : 10; d > 1; --d)
-    if (d != 7 && n % d == 0) return d;
+  for (int d = cap < 12 ? cap : 12; d > 1; --d)
+    if (d != 7 && d != 11 && n % d == 0) return d;
   return 1;
 }
 
 // In-place length-D transforms of the nc columns of a [D][nc] LDS array.
-template <class T, int S, int D>
+template <class T, int S, int D, int NT = kThreads>
 __device__ inline void column_fft(cplx<T>* a, int nc) {
-  for (int c = threadIdx.x; c < nc; c += kThreads) {
+  for (int c = threadIdx.x; c < nc; c += NT) {
     cplx<T> v[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) v[k] = a[k * nc + c];
@@ -85,47 +89,49 @@ __device__ inline void column_fft(cplx<T>* a, int nc) {
   }
 }
 
-// Slab tiles: divisors d <= 10 of the grid size (d = 1 is a no-op).
-template <class T, int S, int N>
+// Slab tiles: divisors d <= 12 of the grid size (d = 1 is a no-op).
+template <class T, int S, int N, int NT = kThreads>
 __device__ inline void column_fft_tile(cplx<T>* a, int d, int nc) {
-  if constexpr (N % 10 == 0) if (d == 10) return column_fft<T, S, 10>(a, nc);
-  if constexpr (N % 9 == 0) if (d == 9) return column_fft<T, S, 9>(a, nc);
-  if constexpr (N % 8 == 0) if (d == 8) return column_fft<T, S, 8>(a, nc);
-  if constexpr (N % 6 == 0) if (d == 6) return column_fft<T, S, 6>(a, nc);
-  if constexpr (N % 5 == 0) if (d == 5) return column_fft<T, S, 5>(a, nc);
-  if constexpr (N % 4 == 0) if (d == 4) return column_fft<T, S, 4>(a, nc);
-  if constexpr (N % 3 == 0) if (d == 3) return column_fft<T, S, 3>(a, nc);
-  if constexpr (N % 2 == 0) if (d == 2) return column_fft<T, S, 2>(a, nc);
+  if constexpr (N % 12 == 0) if (d == 12) return column_fft<T, S, 12, NT>(a, nc);
+  if constexpr (N % 10 == 0) if (d == 10) return column_fft<T, S, 10, NT>(a, nc);
+  if constexpr (N % 9 == 0) if (d == 9) return column_fft<T, S, 9, NT>(a, nc);
+  if constexpr (N % 8 == 0) if (d == 8) return column_fft<T, S, 8, NT>(a, nc);
+  if constexpr (N % 6 == 0) if (d == 6) return column_fft<T, S, 6, NT>(a, nc);
+  if constexpr (N % 5 == 0) if (d == 5) return column_fft<T, S, 5, NT>(a, nc);
+  if constexpr (N % 4 == 0) if (d == 4) return column_fft<T, S, 4, NT>(a, nc);
+  if constexpr (N % 3 == 0) if (d == 3) return column_fft<T, S, 3, NT>(a, nc);
+  if constexpr (N % 2 == 0) if (d == 2) return column_fft<T, S, 2, NT>(a, nc);
 }
 
 // Forward pruned transform of NF fields.  Load(f, x, y, z) returns the
-// field value; acc[f][t] accumulates output o = threadIdx.x + t * kThreads
-// (o < nout) whose packed descriptor is gdesc[t] (pre-loaded by the caller).
+// field value; acc[f][t] accumulates output o = threadIdx.x + t * NT
+// (o < nout; NT threads per workgroup) whose packed descriptor is gdesc[t]
+// (pre-loaded by the caller).
 //
 // The x transform is split as N = M * sx (sx divides N): slab group x2
 // holds the planes x = x2 + M xs, xs < sx.  After the z and y passes of the
 // group, a length-sx FFT across its planes gives, for every kept (ky, kz),
 // Y_x2(q) = sum_xs f(x2 + M xs) w_sx^{q xs}; output kx then needs only
 // w_N^{kx x2} Y_x2(kx mod sx), one product per group instead of sx.
-template <class T, int S, int N, int NF, int OPT, class Load>
+template <class T, int S, int N, int NF, int OPT, int NT = kThreads, class Load>
 __device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax, int sx,
                                       const int (&gdesc)[OPT], int nout,
                                       cplx<T> (&acc)[NF][OPT], const SlabLds<T>& L) {
   const int nk = 2 * kmax + 1, nc = nk * nk, M = N / sx;
   const int tid = threadIdx.x;
-  int off[OPT], kx[OPT];
+  // per output: t2 offset of its residue column (low 24 bits) and kx mod N
+  int ox[OPT];
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
     const int kxm = gdesc[t] & 0xff, kyi = (gdesc[t] >> 8) & 0xff, kzi = gdesc[t] >> 16;
-    kx[t] = kxm;
-    off[t] = ((kxm % sx) * nk + kyi) * nk + kzi;
+    ox[t] = (((kxm % sx) * nk + kyi) * nk + kzi) | (kxm << 24);
   }
   for (int x2 = 0; x2 < M; ++x2) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       if (f >= nf_active) break;
       // z pass: line (xs, y)
-      for (int l = tid; l < sx * N; l += kThreads) {
+      for (int l = tid; l < sx * N; l += NT) {
         const int xs = l / N, y = l - xs * N, x = x2 + M * xs;
         cplx<T> v[N];
 #pragma unroll
@@ -134,15 +140,15 @@ __device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax, i
 #pragma unroll
         for (int z = 0; z < N; ++z) {
           const int kz = (z <= N / 2) ? z : z - N;
-          if (kz >= -kmax && kz <= kmax) L.t1[(xs * nk + kz + kmax) * (N + 1) + y] = v[z];
+          if (kz >= -kmax && kz <= kmax) L.t1[(xs * nk + kz + kmax) * slab_row(N) + y] = v[z];
         }
       }
       __syncthreads();
       // y pass: line (xs, kz)
-      for (int l = tid; l < sx * nk; l += kThreads) {
+      for (int l = tid; l < sx * nk; l += NT) {
         const int xs = l / nk, kzi = l - xs * nk;
         cplx<T> v[N];
-        const cplx<T>* src = L.t1 + (xs * nk + kzi) * (N + 1);
+        const cplx<T>* src = L.t1 + (xs * nk + kzi) * slab_row(N);
 #pragma unroll
         for (int y = 0; y < N; ++y) v[y] = src[y];
         Fft<T, S, N>::run(v);
@@ -154,16 +160,19 @@ __device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax, i
       }
       __syncthreads();
       // x: length-sx FFT across the group's planes, then one product per output
-      column_fft_tile<T, S, N>(L.t2, sx, nc);
+      column_fft_tile<T, S, N, NT>(L.t2, sx, nc);
       if (sx > 1) __syncthreads();
 #pragma unroll
       for (int t = 0; t < OPT; ++t) {
-        const int o = tid + t * kThreads;
-        if (o < nout) acc[f][t] = cfma(L.tw[(kx[t] * x2) % N], L.t2[off[t]], acc[f][t]);
+        const int o = tid + t * NT;
+        if (o < nout)
+          acc[f][t] = cfma(L.tw[((ox[t] >> 24) * x2) % N], L.t2[ox[t] & 0xffffff], acc[f][t]);
       }
-      __syncthreads();
+      // no barrier here: the next z pass writes only t1, and t2 is rewritten
+      // only after the barrier that follows it
     }
   }
+  __syncthreads();
 }
 
 // Inverse transform of NF coefficient vectors given on a sphere whose
@@ -218,7 +227,7 @@ __device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_ac
                                              : cplx<T>{T(0), T(0)};
         }
         Fft<T, 1, N>::run(v);
-        cplx<T>* dst = L.t1 + (xs * nk + kzi) * (N + 1);
+        cplx<T>* dst = L.t1 + (xs * nk + kzi) * slab_row(N);
 #pragma unroll
         for (int y = 0; y < N; ++y) dst[y] = v[y];
       }
@@ -230,16 +239,18 @@ __device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_ac
 #pragma unroll
         for (int z = 0; z < N; ++z) {
           const int kz = (z <= N / 2) ? z : z - N;
-          v[z] = (kz >= -kmax && kz <= kmax) ? L.t1[(xs * nk + kz + kmax) * (N + 1) + y]
+          v[z] = (kz >= -kmax && kz <= kmax) ? L.t1[(xs * nk + kz + kmax) * slab_row(N) + y]
                                              : cplx<T>{T(0), T(0)};
         }
         Fft<T, 1, N>::run(v);
 #pragma unroll
         for (int z = 0; z < N; ++z) st(f, x, y, z, v[z]);
       }
-      __syncthreads();
+      // no barrier here: the next x stage writes only t2, and t1 is rewritten
+      // only after the barriers that follow it
     }
   }
+  __syncthreads();
 }
 
 // Block-wide sum of a double (deterministic order), result valid in thread 0.
