@@ -33,13 +33,21 @@ using namespace ltmp2;
 
 namespace {
 
-struct Round {
+// One fused pair launch: the cells of a round that share a kept-set instance.
+struct Part {
   std::vector<PairCell> cells;  // host copy (for inspection)
   PairCell* d_cells = nullptr;
   long* d_prefix = nullptr;
   long total = 0;
-  int ng_max = 0, kmax_max = 0;
+  int ng_max = 0, kmax_max = 0, kfix = -1;
 };
+using Round = std::vector<Part>;
+
+int round_kmax(const Round& r) {
+  int k = 0;
+  for (const Part& p : r) k = std::max(k, p.kmax_max);
+  return k;
+}
 
 struct Group {
   int n = 0;
@@ -106,29 +114,32 @@ ltmp2_status balloc(ltmp2_batch* b, void** p, size_t bytes) {
 }
 
 template <class T>
-ltmp2_status fused_pair(ltmp2_batch* b, const Group& g, const Round& r, int sx, int wg) {
+ltmp2_status fused_pair(ltmp2_batch* b, const Group& g, const Part& r, int sx, int wg) {
   if (r.total == 0) return LTMP2_OK;
   const GridOps<T>* ops = grid_ops<T>(g.n);
   long nblk = std::min<long>((r.total + 7) / 8 * 8, long(wg) * b->num_cus);
   nblk = std::max<long>(8, nblk / 8 * 8);
-  return ops->pair_multi(r.d_cells, r.d_prefix, int(r.cells.size()), r.ng_max, r.kmax_max, sx,
-                         int(nblk), b->stream);
+  return ops->pair_multi(r.d_cells, r.d_prefix, int(r.cells.size()), r.ng_max, r.kmax_max,
+                         r.kfix, sx, int(nblk), b->stream);
 }
 
-ltmp2_status pair_launch(ltmp2_batch* b, const Group& g, const Round& r, int sx, int wg) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (b->timing && r.total > 0 && hipEventCreate(&e0) == hipSuccess &&
-      hipEventCreate(&e1) == hipSuccess)
-    (void)hipEventRecord(e0, b->stream);
-  const ltmp2_status s = b->prec == LTMP2_FP64 ? fused_pair<double>(b, g, r, sx, wg)
-                                               : fused_pair<float>(b, g, r, sx, wg);
-  if (e1) {
-    (void)hipEventRecord(e1, b->stream);
-    b->marks.push_back({e0, e1});
-  } else if (e0) {
-    (void)hipEventDestroy(e0);
+ltmp2_status pair_launch(ltmp2_batch* b, const Group& g, const Round& rd, int sx, int wg) {
+  for (const Part& r : rd) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (b->timing && r.total > 0 && hipEventCreate(&e0) == hipSuccess &&
+        hipEventCreate(&e1) == hipSuccess)
+      (void)hipEventRecord(e0, b->stream);
+    const ltmp2_status s = b->prec == LTMP2_FP64 ? fused_pair<double>(b, g, r, sx, wg)
+                                                 : fused_pair<float>(b, g, r, sx, wg);
+    if (e1) {
+      (void)hipEventRecord(e1, b->stream);
+      b->marks.push_back({e0, e1});
+    } else if (e0) {
+      (void)hipEventDestroy(e0);
+    }
+    if (s) return s;
   }
-  return s;
+  return LTMP2_OK;
 }
 
 void collect_batch_timing(ltmp2_batch* b) {
@@ -205,8 +216,8 @@ ltmp2_status tune_group(ltmp2_batch* b, Group& g) {
     const int gb = std::min(c->gblock, c->nh);
     if ((s = exchange_block_prepare(c, 0, 0, gb))) return bfail(b, s, "tuning prepare: " + c->err);
   }
-  const int smax = b->prec == LTMP2_FP64 ? grid_ops<double>(g.n)->pair_sx_max(r0.kmax_max)
-                                         : grid_ops<float>(g.n)->pair_sx_max(r0.kmax_max);
+  const int smax = b->prec == LTMP2_FP64 ? grid_ops<double>(g.n)->pair_sx_max(round_kmax(r0))
+                                         : grid_ops<float>(g.n)->pair_sx_max(round_kmax(r0));
   std::vector<int> sxs{smax};
   if (smax > 1) sxs.push_back(slab_tile_at_most(g.n, smax - 1));
   hipEvent_t e0, e1;
@@ -341,42 +352,52 @@ extern "C" ltmp2_status ltmp2_batch_create(int n_cells, const ltmp2_params* para
       off += 2 * es * size_t(c->gblock) * c->no * c->nrp;
     }
     g.sched.assign(g.max_ntau, std::vector<Round>(g.rounds));
+    int (*kept)(int) = b->prec == LTMP2_FP64 ? grid_ops<double>(g.n)->pair_kept
+                                             : grid_ops<float>(g.n)->pair_kept;
     for (int it = 0; it < g.max_ntau; ++it)
       for (int r = 0; r < g.rounds; ++r) {
-        Round& rd = g.sched[it][r];
-        std::vector<long> prefix{0};
+        // one part per kept-set instance among the round's active cells
+        std::map<int, std::vector<int>> by_kept;
         for (int ci : g.cells) {
           ltmp2_ctx* c = b->cells[ci];
-          if (it >= c->ntau) continue;
-          const int g0 = r * c->gblock;
-          if (g0 >= c->nh) continue;
-          const int gb = std::min(c->gblock, c->nh - g0);
-          rd.cells.push_back(PairCell{c->d_psi, c->d_w, c->d_pairs, c->d_gdesc, c->d_v,
-                                      c->d_xpart + size_t(g0) * c->npairs, c->nrp, c->no,
-                                      c->npairs, gb, c->ng, c->kmax_aux, c->dV * c->dV});
-          prefix.push_back(prefix.back() + long(c->npairs) * gb);
-          rd.ng_max = std::max(rd.ng_max, c->ng);
-          rd.kmax_max = std::max(rd.kmax_max, c->kmax_aux);
+          if (it >= c->ntau || r * c->gblock >= c->nh) continue;
+          by_kept[kept(c->kmax_aux)].push_back(ci);
         }
-        rd.total = prefix.back();
-        if (rd.cells.empty()) continue;
-        void *pc = nullptr, *pp = nullptr;
-        if ((s = balloc(b, &pc, sizeof(PairCell) * rd.cells.size())) ||
-            (s = balloc(b, &pp, sizeof(long) * prefix.size()))) {
-          ltmp2_batch_destroy(b);
-          return bfail(nullptr, s, "schedule allocation failed");
-        }
-        rd.d_cells = static_cast<PairCell*>(pc);
-        rd.d_prefix = static_cast<long*>(pp);
-        if (hipMemcpy(pc, rd.cells.data(), sizeof(PairCell) * rd.cells.size(),
-                      hipMemcpyHostToDevice) ||
-            hipMemcpy(pp, prefix.data(), sizeof(long) * prefix.size(), hipMemcpyHostToDevice)) {
-          ltmp2_batch_destroy(b);
-          return bfail(nullptr, LTMP2_EDEVICE, "schedule upload failed");
+        for (auto& kv : by_kept) {
+          Part rd;
+          rd.kfix = kv.first;
+          std::vector<long> prefix{0};
+          for (int ci : kv.second) {
+            ltmp2_ctx* c = b->cells[ci];
+            const int g0 = r * c->gblock;
+            const int gb = std::min(c->gblock, c->nh - g0);
+            rd.cells.push_back(PairCell{c->d_psi, c->d_w, c->d_pairs, c->d_gdesc, c->d_v,
+                                        c->d_xpart + size_t(g0) * c->npairs, c->nrp, c->no,
+                                        c->npairs, gb, c->ng, c->kmax_aux, c->dV * c->dV});
+            prefix.push_back(prefix.back() + long(c->npairs) * gb);
+            rd.ng_max = std::max(rd.ng_max, c->ng);
+            rd.kmax_max = std::max(rd.kmax_max, c->kmax_aux);
+          }
+          rd.total = prefix.back();
+          void *pc = nullptr, *pp = nullptr;
+          if ((s = balloc(b, &pc, sizeof(PairCell) * rd.cells.size())) ||
+              (s = balloc(b, &pp, sizeof(long) * prefix.size()))) {
+            ltmp2_batch_destroy(b);
+            return bfail(nullptr, s, "schedule allocation failed");
+          }
+          rd.d_cells = static_cast<PairCell*>(pc);
+          rd.d_prefix = static_cast<long*>(pp);
+          if (hipMemcpy(pc, rd.cells.data(), sizeof(PairCell) * rd.cells.size(),
+                        hipMemcpyHostToDevice) ||
+              hipMemcpy(pp, prefix.data(), sizeof(long) * prefix.size(), hipMemcpyHostToDevice)) {
+            ltmp2_batch_destroy(b);
+            return bfail(nullptr, LTMP2_EDEVICE, "schedule upload failed");
+          }
+          g.sched[it][r].push_back(std::move(rd));
         }
       }
     // largest slab tile allowed by shared memory for this group
-    const int km = g.sched[0][0].kmax_max;
+    const int km = round_kmax(g.sched[0][0]);
     g.sx = b->prec == LTMP2_FP64 ? grid_ops<double>(g.n)->pair_sx_max(km)
                                  : grid_ops<float>(g.n)->pair_sx_max(km);
   }

@@ -35,10 +35,13 @@ struct GridOps {
   ltmp2_status (*pair)(const T* psi, long ld, const cplx<T>* w, int no, const int* pairs,
                        int npairs, int gb, const int* gdesc, int ng, const double* v, int kmax,
                        double dV2, double* xpart, hipStream_t st);
-  // persistent multi-cell pair launch (device arrays cells[ncells], prefix[ncells + 1])
+  // persistent multi-cell pair launch (device arrays cells[ncells], prefix[ncells + 1]);
+  // all cells share the kept-set instance kfix (pair_kept)
   ltmp2_status (*pair_multi)(const PairCell* cells, const long* prefix, int ncells, int ng_max,
-                             int kmax_max, int sx, int nblocks, hipStream_t st);
+                             int kmax_max, int kfix, int sx, int nblocks, hipStream_t st);
   int (*pair_sx_max)(int kmax);
+  // kept-set instance of the pair kernels for a cell's kmax (or -1: runtime form)
+  int (*pair_kept)(int kmax);
 };
 
 template <class T>

@@ -1,6 +1,7 @@
 // Transform kernels instantiated for one grid size n = LTMP2_N.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -148,18 +149,39 @@ ltmp2_status wstates(const T* P, int npw, const int* wq, const signed char* wsgn
                 wq, wsgn, sc, sx, scale, w, ld);
 }
 
+// Kept-set instance of the pair kernels for a cell: kwin(N), kwin(N) - 1 or
+// the runtime form (-1).
+inline int pair_kfix(int kmax) {
+  return (kmax == kwin(N) || (kwin(N) > 1 && kmax == kwin(N) - 1)) ? kmax : -1;
+}
+
+template <class T, int NT, int OPT, int KM>
+ltmp2_status pair_go(const PairCell& pc, int sx, hipStream_t st) {
+  const long total = long(pc.npairs) * pc.gb;
+  return launch_nt(k_pair<T, N, OPT, NT, KM>, dim3(unsigned((total + 7) / 8 * 8)), NT,
+                   slab_lds_bytes<T>(N, 2 * pc.kmax + 1, sx), st, pc, sx);
+}
+
+template <class T, int NT, int OPT>
+ltmp2_status pair_km(const PairCell& pc, int sx, hipStream_t st) {
+  constexpr int kw = kwin(N);
+  const int kf = pair_kfix(pc.kmax);
+  if (kf == kw) return pair_go<T, NT, OPT, kw>(pc, sx, st);
+  if constexpr (kw > 1)
+    if (kf == kw - 1) return pair_go<T, NT, OPT, kw - 1>(pc, sx, st);
+  return pair_go<T, NT, OPT, -1>(pc, sx, st);
+}
+
 template <class T>
 struct PairF {
   template <int OPT>
   struct F {
-    static ltmp2_status go(const T* psi, long ld, const cplx<T>* w, int no, const int* pairs,
-                           int npairs, int gb, const int* gdesc, int ng, const double* v, int kmax,
-                           double dV2, double* xpart, hipStream_t st) {
-      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
-      PairCell pc{psi, w, pairs, gdesc, v, xpart, ld, no, npairs, gb, ng, kmax, dV2};
-      const long total = long(npairs) * gb;
-      const unsigned nblk = unsigned((total + 7) / 8 * 8);
-      return launch(k_pair<T, N, OPT>, dim3(nblk), slab_lds_bytes<T>(N, nk, sx), st, pc, sx);
+    static ltmp2_status go(const PairCell& pc, int sx, hipStream_t st) {
+      if constexpr (sizeof(T) == sizeof(float) && OPT > 9) {
+        return LTMP2_EINVAL;  // FP32 takes the 512-thread form above 9 outputs
+      } else {
+        return pair_km<T, kThreads, OPT>(pc, sx, st);
+      }
     }
   };
 };
@@ -167,47 +189,70 @@ template <class T>
 ltmp2_status pair(const T* psi, long ld, const cplx<T>* w, int no, const int* pairs, int npairs,
                   int gb, const int* gdesc, int ng, const double* v, int kmax, double dV2,
                   double* xpart, hipStream_t st) {
+  PairCell pc{psi, w, pairs, gdesc, v, xpart, ld, no, npairs, gb, ng, kmax, dV2};
   if constexpr (sizeof(T) == sizeof(float)) {
     if (ng > 9 * kThreads) {
       if (ng > kWideOpt * kWideNT) return LTMP2_EINVAL;
-      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk, 12);
-      PairCell pc{psi, w, pairs, gdesc, v, xpart, ld, no, npairs, gb, ng, kmax, dV2};
-      const long total = long(npairs) * gb;
-      return launch_nt(k_pair<T, N, kWideOpt, kWideNT>, dim3(unsigned((total + 7) / 8 * 8)),
-                       kWideNT, slab_lds_bytes<T>(N, nk, sx), st, pc, sx);
+      return pair_km<T, kWideNT, kWideOpt>(pc, choose_sx<T>(2 * kmax + 1, 12), st);
     }
   }
-  return by_opt<PairF<T>::template F>(ng, psi, ld, w, no, pairs, npairs, gb, gdesc, ng, v, kmax,
-                                      dV2, xpart, st);
+  return by_opt<PairF<T>::template F>(ng, pc, choose_sx<T>(2 * kmax + 1), st);
+}
+
+template <class T, int NT, int OPT, int KM>
+ltmp2_status pair_multi_go(const PairCell* cells, const long* prefix, int ncells, int kmax_max,
+                           int sx, int nblocks, hipStream_t st) {
+  return launch_nt(k_pair_multi<T, N, OPT, NT, KM>, dim3(unsigned(nblocks)), NT,
+                   slab_lds_bytes<T>(N, 2 * kmax_max + 1, sx), st, cells, prefix, ncells, sx);
+}
+
+template <class T, int NT, int OPT>
+ltmp2_status pair_multi_km(int kfix, const PairCell* cells, const long* prefix, int ncells,
+                           int kmax_max, int sx, int nblocks, hipStream_t st) {
+  constexpr int kw = kwin(N);
+  if (kfix >= 0 && kfix != kmax_max) return LTMP2_EINVAL;
+  if (kfix == kw) return pair_multi_go<T, NT, OPT, kw>(cells, prefix, ncells, kmax_max, sx, nblocks, st);
+  if constexpr (kw > 1)
+    if (kfix == kw - 1)
+      return pair_multi_go<T, NT, OPT, kw - 1>(cells, prefix, ncells, kmax_max, sx, nblocks, st);
+  if (kfix >= 0) return LTMP2_EINVAL;
+  return pair_multi_go<T, NT, OPT, -1>(cells, prefix, ncells, kmax_max, sx, nblocks, st);
 }
 
 template <class T>
 struct PairMultiF {
   template <int OPT>
   struct F {
-    static ltmp2_status go(const PairCell* cells, const long* prefix, int ncells, int kmax_max,
-                           int sx, int nblocks, hipStream_t st) {
-      const int nk = 2 * kmax_max + 1;
+    static ltmp2_status go(int kfix, const PairCell* cells, const long* prefix, int ncells,
+                           int kmax_max, int sx, int nblocks, hipStream_t st) {
       if (sx < 1 || N % sx != 0 || sx > 10) return LTMP2_EINVAL;
-      return launch(k_pair_multi<T, N, OPT>, dim3(unsigned(nblocks)), slab_lds_bytes<T>(N, nk, sx),
-                    st, cells, prefix, ncells, sx);
+      if constexpr (sizeof(T) == sizeof(float) && OPT > 9) {
+        return LTMP2_EINVAL;
+      } else {
+        return pair_multi_km<T, kThreads, OPT>(kfix, cells, prefix, ncells, kmax_max, sx, nblocks,
+                                               st);
+      }
     }
   };
 };
+// Several cells of one grid size in one persistent launch; kfix is the kept
+// set all of them share (kwin(N) or kwin(N) - 1, see pair_kfix) or -1.
 template <class T>
 ltmp2_status pair_multi(const PairCell* cells, const long* prefix, int ncells, int ng_max,
-                        int kmax_max, int sx, int nblocks, hipStream_t st) {
+                        int kmax_max, int kfix, int sx, int nblocks, hipStream_t st) {
   if constexpr (sizeof(T) == sizeof(float)) {
     if (ng_max > 9 * kThreads) {
       if (ng_max > kWideOpt * kWideNT || sx < 1 || N % sx != 0 || sx > 12) return LTMP2_EINVAL;
-      return launch_nt(k_pair_multi<T, N, kWideOpt, kWideNT>, dim3(unsigned(nblocks)), kWideNT,
-                       slab_lds_bytes<T>(N, 2 * kmax_max + 1, sx), st, cells, prefix, ncells,
-                       sx);
+      return pair_multi_km<T, kWideNT, kWideOpt>(kfix, cells, prefix, ncells, kmax_max, sx,
+                                                  nblocks, st);
     }
   }
-  return by_opt<PairMultiF<T>::template F>(ng_max, cells, prefix, ncells, kmax_max, sx, nblocks,
-                                           st);
+  return by_opt<PairMultiF<T>::template F>(ng_max, kfix, cells, prefix, ncells, kmax_max, sx,
+                                           nblocks, st);
 }
+
+// Kept-set instance (kwin(N), kwin(N) - 1 or -1) the pair kernels use for kmax.
+int pair_kept_instance(int kmax) { return pair_kfix(kmax); }
 
 // Largest slab group of the pair transform that fits the shared memory.
 template <class T>
@@ -232,7 +277,7 @@ int pair_sx_max(int kmax) {
                                 const int*, int, const double*, int, double, double*,          \
                                 hipStream_t);                                                  \
   template ltmp2_status pair_multi<T>(const PairCell*, const long*, int, int, int, int, int,   \
-                                      hipStream_t);                                            \
+                                      int, hipStream_t);                                       \
   template int pair_sx_max<T>(int);
 LTMP2_INST(double)
 LTMP2_INST(float)
@@ -246,10 +291,10 @@ extern const GridOps<double> LTMP2_CAT(kGridOpsD_, LTMP2_N);
 extern const GridOps<float> LTMP2_CAT(kGridOpsF_, LTMP2_N);
 const GridOps<double> LTMP2_CAT(kGridOpsD_, LTMP2_N) = {
     orbitals<double>, overlap<double>, chi_rows<double>, chi_cols<double>, wstates<double>,
-    pair<double>, pair_multi<double>, pair_sx_max<double>};
+    pair<double>, pair_multi<double>, pair_sx_max<double>, pair_kept_instance};
 const GridOps<float> LTMP2_CAT(kGridOpsF_, LTMP2_N) = {
     orbitals<float>, overlap<float>, chi_rows<float>, chi_cols<float>, wstates<float>,
-    pair<float>, pair_multi<float>, pair_sx_max<float>};
+    pair<float>, pair_multi<float>, pair_sx_max<float>, pair_kept_instance};
 #endif
 
 }  // namespace ltmp2

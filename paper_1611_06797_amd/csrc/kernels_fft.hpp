@@ -238,10 +238,12 @@ struct PairCell {
   double dV2;
 };
 
-template <class T, int N, int OPT, int NT = kThreads>
+// KM >= 0: the cell's kept set is kmax = KM, known at compile time (see kwin);
+// KM = -1: runtime kmax.
+template <class T, int N, int OPT, int NT = kThreads, int KM = -1>
 __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void* smem,
                                  double* red) {
-  const int nk = 2 * pc.kmax + 1;
+  const int nk = 2 * (KM >= 0 ? KM : pc.kmax) + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, -1, N>(L.tw);
   const int i = pc.pairs[p] & 0xffff, j = pc.pairs[p] >> 16;
@@ -267,7 +269,8 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
     const cplx<T> b = (f == 0) ? wj[r] : wi[r];
     return cplx<T>{a * b.x, a * b.y};
   };
-  forward_pruned<T, -1, N, 2, OPT, NT>(ld_, (i == j) ? 1 : 2, pc.kmax, sx, gd, pc.ng, acc, L);
+  forward_pruned<T, -1, N, 2, OPT, NT, KM>(ld_, (i == j) ? 1 : 2, pc.kmax, sx, gd, pc.ng, acc,
+                                           L);
   double s = 0.0;
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
@@ -290,7 +293,7 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
 // gets a contiguous range of the (G', pair) list, whose pairs come in 8 x 8
 // blocks of (i, j), so the workgroups resident on one XCD share a handful of
 // psi_i and w_j^{(G')} in that XCD's L2.
-template <class T, int N, int OPT, int NT = kThreads>
+template <class T, int N, int OPT, int NT = kThreads, int KM = -1>
 __global__ __launch_bounds__(NT) void k_pair(PairCell pc, int sx) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[NT / 64];
@@ -299,14 +302,14 @@ __global__ __launch_bounds__(NT) void k_pair(PairCell pc, int sx) {
   const long t = long(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= total) return;
   const int gl = int(t / pc.npairs);
-  pair_item<T, N, OPT, NT>(pc, gl, int(t - long(gl) * pc.npairs), sx, smem, red);
+  pair_item<T, N, OPT, NT, KM>(pc, gl, int(t - long(gl) * pc.npairs), sx, smem, red);
 }
 
 // Several cells of the same grid in one persistent launch: the work list is
 // the concatenation of every cell's (G', pair) items (prefix[c] = first item
 // of cell c); each XCD owns a contiguous range and its workgroups stride
 // through it, so every workgroup exits after a bounded number of items.
-template <class T, int N, int OPT, int NT = kThreads>
+template <class T, int N, int OPT, int NT = kThreads, int KM = -1>
 __global__ __launch_bounds__(NT) void k_pair_multi(const PairCell* __restrict__ cells,
                                                          const long* __restrict__ prefix,
                                                          int ncells, int sx) {
@@ -326,7 +329,7 @@ __global__ __launch_bounds__(NT) void k_pair_multi(const PairCell* __restrict__ 
     const PairCell pc = cells[lo];
     const long u = t - prefix[lo];
     const int gl = int(u / pc.npairs);
-    pair_item<T, N, OPT, NT>(pc, gl, int(u - long(gl) * pc.npairs), sx, smem, red);
+    pair_item<T, N, OPT, NT, KM>(pc, gl, int(u - long(gl) * pc.npairs), sx, smem, red);
     __syncthreads();
   }
 }

@@ -69,6 +69,12 @@ __device__ inline void fill_twiddles(cplx<T>* tw) {
   for (int e = threadIdx.x; e < N; e += blockDim.x) tw[e] = TwiddleTable<T, S, N>::v[e];
 }
 
+// Compile-time pruning window of a grid: the largest kept set an alias-free
+// transform grid can have (N >= 2 k_orb + k_aux + 1 >= 3 k_aux + 1).  Pair
+// transforms with kept set kmax = kwin(N) or kwin(N) - 1 run kernels compiled
+// for that kmax, so which FFT outputs are stored needs no per-element branch.
+__host__ __device__ constexpr int kwin(int n) { return (n - 1) / 3; }
+
 // Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10, 12).
 __host__ __device__ constexpr int slab_tile_at_most(int n, int cap) {
   for (int d = cap < 12 ? cap : 12; d > 1; --d)
@@ -113,10 +119,12 @@ __device__ inline void column_fft_tile(cplx<T>* a, int d, int nc) {
 // group, a length-sx FFT across its planes gives, for every kept (ky, kz),
 // Y_x2(q) = sum_xs f(x2 + M xs) w_sx^{q xs}; output kx then needs only
 // w_N^{kx x2} Y_x2(kx mod sx), one product per group instead of sx.
-template <class T, int S, int N, int NF, int OPT, int NT = kThreads, class Load>
-__device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax, int sx,
+// KM >= 0 fixes kmax = KM at compile time (see kwin).
+template <class T, int S, int N, int NF, int OPT, int NT = kThreads, int KM = -1, class Load>
+__device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax_rt, int sx,
                                       const int (&gdesc)[OPT], int nout,
                                       cplx<T> (&acc)[NF][OPT], const SlabLds<T>& L) {
+  const int kmax = KM >= 0 ? KM : kmax_rt;
   const int nk = 2 * kmax + 1, nc = nk * nk, M = N / sx;
   const int tid = threadIdx.x;
   // per output: t2 offset of its residue column (low 24 bits) and kx mod N
