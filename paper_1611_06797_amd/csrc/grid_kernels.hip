@@ -140,13 +140,19 @@ ltmp2_status chi_cols(const cplx<T>* chihat, long ld, const int* gdesc, int ng, 
 template <class T>
 ltmp2_status wstates(const T* P, int npw, const int* wq, const signed char* wsgn, SphereCols sc,
                      int nitems, double scale, cplx<T>* w, long ld, hipStream_t st) {
-  const int nk = 2 * sc.kmax + 1;
-  const size_t extra = sizeof(cplx<T>) * size_t(npw);
-  int sx = slab_tile_at_most(N, 10);
-  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) + extra > kLdsCap)
-    sx = slab_tile_at_most(N, sx - 1);
-  return launch(k_wstates<T, N>, dim3(nitems), slab_lds_bytes<T>(N, nk, sx) + extra, st, P, npw,
-                wq, wsgn, sc, sx, scale, w, ld);
+  const int nk = 2 * sc.kmax + 1, sx = choose_sx<T>(nk);
+  const size_t lds = slab_lds_bytes<T>(N, nk, sx);
+  // orbital spheres at the alias-free window and one below run kernels
+  // compiled for that kmax (no per-element branches in the y and z stages)
+  constexpr int ko = korb_win(N);
+  if (sc.kmax == ko)
+    return launch(k_wstates<T, N, ko>, dim3(nitems), lds, st, P, npw, wq, wsgn, sc, sx, scale, w,
+                  ld);
+  if constexpr (ko > 1)
+    if (sc.kmax == ko - 1)
+      return launch(k_wstates<T, N, ko - 1>, dim3(nitems), lds, st, P, npw, wq, wsgn, sc, sx,
+                    scale, w, ld);
+  return launch(k_wstates<T, N>, dim3(nitems), lds, st, P, npw, wq, wsgn, sc, sx, scale, w, ld);
 }
 
 // Kept-set instance of the pair kernels for a cell: kwin(N), kwin(N) - 1 or

@@ -176,18 +176,18 @@ __global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict
 // with W_j(G) rebuilt from the real-basis product P = C Psi_v:
 //   P[(g, j, 0)][q] = sum_a Re C_ja B[a][q],  P[(g, j, 1)][q] = sum_a Im C_ja B[a][q],
 // where B[a][q] holds Re c_a(0), Re c_a(G_k), Im c_a(G_k) for the half sphere.
-// W_j(G) is rebuilt once per item into shared memory (after the slab buffers).
+// W_j(G) is gathered from P where the x stage needs it.
 // Entry e of the sphere (column order) uses wq[e] = q_re | (q_im + 1) << 16
 // and the sign s = +1 for G_k, -1 for -G_k (c_a(-G) = conj c_a(G)):
 //   W(G) = (P_re[q_re] - s P_im[q_im]) + i (P_im[q_re] + s P_re[q_im]).
-template <class T, int N>
+template <class T, int N, int KO = -1>
 __global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, int npw,
                                                       const int* __restrict__ wq,
                                                       const signed char* __restrict__ wsgn,
                                                       SphereCols sc, int sx, double scale,
                                                       cplx<T>* __restrict__ w, long ld) {
   extern __shared__ __align__(16) char smem[];
-  const int nk = 2 * sc.kmax + 1;
+  const int nk = 2 * (KO >= 0 ? KO : sc.kmax) + 1;
   SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, 1, N>(L.tw);
   for (int e = threadIdx.x; e < sx * nk * nk; e += kThreads) L.t2[e] = {T(0), T(0)};
@@ -196,9 +196,9 @@ __global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, i
   const T* pre = P + (2 * item) * long(npw);
   const T* pim = pre + npw;
   cplx<T>* out = w + item * ld;
-  // W_j(G) for the whole sphere, staged once in shared memory
-  cplx<T>* Wl = L.tw + N;
-  for (int e = threadIdx.x; e < npw; e += kThreads) {
+  // W_j(G) of sphere entry e, gathered from the real basis (each entry is
+  // used once per slab group)
+  auto cf = [&](int, int e) {
     const int q = wq[e];
     const int qr = q & 0xffff, qi = (q >> 16) - 1;
     const T s = T(wsgn[e]);
@@ -207,14 +207,12 @@ __global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, i
       re -= s * pim[qi];
       im += s * pre[qi];
     }
-    Wl[e] = {re, im};
-  }
-  __syncthreads();
-  auto cf = [&](int, int e) { return Wl[e]; };
+    return cplx<T>{re, im};
+  };
   auto st = [&](int, int x, int y, int z, cplx<T> v) {
     out[(x * N + z) * N + y] = {T(scale) * v.x, T(scale) * v.y};
   };
-  inverse_sphere<T, N, 1>(cf, st, 1, sc.kmax, sx, sc.ncol, sc.cdesc, sc.cstart, sc.ckx, L);
+  inverse_sphere<T, N, 1, KO>(cf, st, 1, sc.kmax, sx, sc.ncol, sc.cdesc, sc.cstart, sc.ckx, L);
 }
 
 // ---------------------------------------------------------------------------

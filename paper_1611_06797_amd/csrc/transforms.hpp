@@ -75,6 +75,10 @@ __device__ inline void fill_twiddles(cplx<T>* tw) {
 // for that kmax, so which FFT outputs are stored needs no per-element branch.
 __host__ __device__ constexpr int kwin(int n) { return (n - 1) / 3; }
 
+// The same for the orbital sphere of the inverse transforms: with the
+// auxiliary window kwin(N), an alias-free grid allows k_orb <= korb_win(N).
+__host__ __device__ constexpr int korb_win(int n) { return (n - 1 - kwin(n)) / 2; }
+
 // Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10, 12).
 __host__ __device__ constexpr int slab_tile_at_most(int n, int cap) {
   for (int d = cap < 12 ? cap : 12; d > 1; --d)
@@ -195,10 +199,12 @@ __device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax_rt
 // group x2 = planes x2 + M xs): per column and residue q < sx,
 // Z(q) = sum_{kx = q mod sx} c(kx) w_N^{kx x2}, then a length-sx FFT over q
 // gives the group's planes.
-template <class T, int N, int NF, class Coef, class Store>
-__device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_active, int kmax,
-                                      int sx, int ncol, const int* cdesc, const int* cstart,
-                                      const int* ckx, const SlabLds<T>& L) {
+// KO >= 0 fixes kmax = KO at compile time (see korb_win).
+template <class T, int N, int NF, int KO = -1, class Coef, class Store>
+__device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_active,
+                                      int kmax_rt, int sx, int ncol, const int* cdesc,
+                                      const int* cstart, const int* ckx, const SlabLds<T>& L) {
+  const int kmax = KO >= 0 ? KO : kmax_rt;
   const int nk = 2 * kmax + 1, nc = nk * nk, M = N / sx;
   const int tid = threadIdx.x;
   for (int x2 = 0; x2 < M; ++x2) {
