@@ -16,11 +16,20 @@ namespace {
 
 constexpr int N = LTMP2_N;
 constexpr size_t kLdsCap = 150 * 1024;
+constexpr size_t kLdsHalf = 78 * 1024;
 
 template <class T>
 int choose_sx(int nk, int cap = 10) {
   int sx = slab_tile_at_most(N, cap);
   while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) > kLdsCap) sx = slab_tile_at_most(N, sx - 1);
+  return sx;
+}
+
+// The same for the forward transforms (z-pass buffer only, see fwd_lds).
+template <class T>
+int choose_sx_fwd(int nk, int cap = 10) {
+  int sx = slab_tile_at_most(N, cap);
+  while (sx > 1 && fwd_lds_bytes<T>(N, nk, sx) > kLdsCap) sx = slab_tile_at_most(N, sx - 1);
   return sx;
 }
 
@@ -84,9 +93,9 @@ struct OverlapF {
     static ltmp2_status go(const T* psi, long ld, int no, int nv, const int* gdesc, int nh,
                            int kmax, double dV, cplx<T>* nd, hipStream_t st) {
       constexpr int NF = 4;
-      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
+      const int nk = 2 * kmax + 1, sx = choose_sx_fwd<T>(nk);
       return launch(k_overlap<T, N, NF, OPT>, dim3((no + NF - 1) / NF, nv),
-                    slab_lds_bytes<T>(N, nk, sx), st, psi, ld, no, gdesc, nh, kmax, sx, dV, nd);
+                    fwd_lds_bytes<T>(N, nk, sx), st, psi, ld, no, gdesc, nh, kmax, sx, dV, nd);
     }
   };
 };
@@ -103,9 +112,9 @@ struct ChiRowsF {
     static ltmp2_status go(const T* chi, long ld, int nr, const int* gdesc, int nh, int kmax,
                            double dV, cplx<T>* chihat, hipStream_t st) {
       constexpr int NF = 2;
-      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
+      const int nk = 2 * kmax + 1, sx = choose_sx_fwd<T>(nk);
       return launch(k_chi_rows<T, N, NF, OPT>, dim3((nr + NF - 1) / NF),
-                    slab_lds_bytes<T>(N, nk, sx), st, chi, ld, nr, gdesc, nh, kmax, sx, dV,
+                    fwd_lds_bytes<T>(N, nk, sx), st, chi, ld, nr, gdesc, nh, kmax, sx, dV,
                     chihat);
     }
   };
@@ -123,8 +132,8 @@ struct ChiColsF {
     static ltmp2_status go(const cplx<T>* chihat, long ld, const int* gdesc, int ng, int nh,
                            const double* v, int kmax, double dV, double* pd,
                            cplx<double>* chi_out, hipStream_t st) {
-      const int nk = 2 * kmax + 1, sx = choose_sx<T>(nk);
-      return launch(k_chi_cols<T, N, OPT>, dim3(nh), slab_lds_bytes<T>(N, nk, sx), st, chihat, ld,
+      const int nk = 2 * kmax + 1, sx = choose_sx_fwd<T>(nk);
+      return launch(k_chi_cols<T, N, OPT>, dim3(nh), fwd_lds_bytes<T>(N, nk, sx), st, chihat, ld,
                     gdesc, ng, nh, v, kmax, sx, dV, pd, chi_out);
     }
   };
@@ -140,7 +149,10 @@ ltmp2_status chi_cols(const cplx<T>* chihat, long ld, const int* gdesc, int ng, 
 template <class T>
 ltmp2_status wstates(const T* P, int npw, const int* wq, const signed char* wsgn, SphereCols sc,
                      int nitems, double scale, cplx<T>* w, long ld, hipStream_t st) {
-  const int nk = 2 * sc.kmax + 1, sx = choose_sx<T>(nk);
+  // at most half the CU's shared memory, so that two workgroups fit
+  const int nk = 2 * sc.kmax + 1;
+  int sx = slab_tile_at_most(N, 10);
+  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) > kLdsHalf) sx = slab_tile_at_most(N, sx - 1);
   const size_t lds = slab_lds_bytes<T>(N, nk, sx);
   // orbital spheres at the alias-free window and one below run kernels
   // compiled for that kmax (no per-element branches in the y and z stages)
@@ -165,7 +177,7 @@ template <class T, int NT, int OPT, int KM>
 ltmp2_status pair_go(const PairCell& pc, int sx, hipStream_t st) {
   const long total = long(pc.npairs) * pc.gb;
   return launch_nt(k_pair<T, N, OPT, NT, KM>, dim3(unsigned((total + 7) / 8 * 8)), NT,
-                   slab_lds_bytes<T>(N, 2 * pc.kmax + 1, sx), st, pc, sx);
+                   fwd_lds_bytes<T>(N, 2 * pc.kmax + 1, sx), st, pc, sx);
 }
 
 template <class T, int NT, int OPT>
@@ -199,17 +211,17 @@ ltmp2_status pair(const T* psi, long ld, const cplx<T>* w, int no, const int* pa
   if constexpr (sizeof(T) == sizeof(float)) {
     if (ng > 9 * kThreads) {
       if (ng > kWideOpt * kWideNT) return LTMP2_EINVAL;
-      return pair_km<T, kWideNT, kWideOpt>(pc, choose_sx<T>(2 * kmax + 1, 12), st);
+      return pair_km<T, kWideNT, kWideOpt>(pc, choose_sx_fwd<T>(2 * kmax + 1, 12), st);
     }
   }
-  return by_opt<PairF<T>::template F>(ng, pc, choose_sx<T>(2 * kmax + 1), st);
+  return by_opt<PairF<T>::template F>(ng, pc, choose_sx_fwd<T>(2 * kmax + 1), st);
 }
 
 template <class T, int NT, int OPT, int KM>
 ltmp2_status pair_multi_go(const PairCell* cells, const long* prefix, int ncells, int kmax_max,
                            int sx, int nblocks, hipStream_t st) {
   return launch_nt(k_pair_multi<T, N, OPT, NT, KM>, dim3(unsigned(nblocks)), NT,
-                   slab_lds_bytes<T>(N, 2 * kmax_max + 1, sx), st, cells, prefix, ncells, sx);
+                   fwd_lds_bytes<T>(N, 2 * kmax_max + 1, sx), st, cells, prefix, ncells, sx);
 }
 
 template <class T, int NT, int OPT>
@@ -263,7 +275,7 @@ int pair_kept_instance(int kmax) { return pair_kfix(kmax); }
 // Largest slab group of the pair transform that fits the shared memory.
 template <class T>
 int pair_sx_max(int kmax) {
-  return choose_sx<T>(2 * kmax + 1);
+  return choose_sx_fwd<T>(2 * kmax + 1);
 }
 
 // Explicit instantiation in both compilation passes, so the device pass

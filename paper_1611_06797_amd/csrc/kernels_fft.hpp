@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kThreads) void k_overlap(const T* __restrict__ psi,
                                                       cplx<T>* __restrict__ nd) {
   extern __shared__ __align__(16) char smem[];
   const int nk = 2 * kmax + 1;
-  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  SlabLds<T> L = fwd_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, -1, N>(L.tw);
   const int j0 = blockIdx.x * NF;
   const int a = blockIdx.y;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_chi_rows(const T* __restrict__ chi
                                                        cplx<T>* __restrict__ chihat) {
   extern __shared__ __align__(16) char smem[];
   const int nk = 2 * kmax + 1;
-  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  SlabLds<T> L = fwd_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, 1, N>(L.tw);
   const int r0 = blockIdx.x * NF;
   const int nf = min(NF, nr - r0);
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[kThreads / 64];
   const int nk = 2 * kmax + 1;
-  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  SlabLds<T> L = fwd_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, -1, N>(L.tw);
   const int g = blockIdx.x;
   const cplx<T>* col = chihat + long(g) * ld;
@@ -242,7 +242,7 @@ template <class T, int N, int OPT, int NT = kThreads, int KM = -1>
 __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void* smem,
                                  double* red) {
   const int nk = 2 * (KM >= 0 ? KM : pc.kmax) + 1;
-  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  SlabLds<T> L = fwd_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, -1, N>(L.tw);
   const int i = pc.pairs[p] & 0xffff, j = pc.pairs[p] >> 16;
   const T* psi = static_cast<const T*>(pc.psi);

@@ -55,6 +55,23 @@ __device__ inline SlabLds<T> slab_lds(void* base, int n, int nk, int sx) {
   return s;
 }
 
+// Forward transforms keep everything in the z-pass buffer: the y pass
+// writes its kept outputs back into the row it read, so the layout is
+// t1 [SX][nk][slab_row(n)] followed by the twiddles.
+template <class T>
+__host__ __device__ inline size_t fwd_lds_bytes(int n, int nk, int sx) {
+  return sizeof(cplx<T>) * (size_t(sx) * nk * slab_row(n) + n);
+}
+
+template <class T>
+__device__ inline SlabLds<T> fwd_lds(void* base, int n, int nk, int sx) {
+  SlabLds<T> s;
+  s.t1 = reinterpret_cast<cplx<T>*>(base);
+  s.t2 = nullptr;
+  s.tw = s.t1 + size_t(sx) * nk * slab_row(n);
+  return s;
+}
+
 // exp(S 2 pi i e / N), e = 0..N-1, as a compile-time table in constant memory.
 template <class T, int S, int N, class Seq = std::make_integer_sequence<int, N>>
 struct TwiddleTable;
@@ -113,6 +130,38 @@ __device__ inline void column_fft_tile(cplx<T>* a, int d, int nc) {
   if constexpr (N % 2 == 0) if (d == 2) return column_fft<T, S, 2, NT>(a, nc);
 }
 
+// Length-D transforms across the planes of the forward layout: column
+// (kzi, kyi) of plane xs sits at a[xs * pstride + kzi * R + kyi].
+template <class T, int S, int D, int NT>
+__device__ inline void column_fft_rows(cplx<T>* a, int nk, int R, int pstride) {
+  // c / nk by a multiply-high: exact for c < nk^2 <= 2^12 (the error of the
+  // rounded-up reciprocal stays below 2^32 / c)
+  const unsigned inv = 0xffffffffu / unsigned(nk) + 1u;
+  for (int c = threadIdx.x; c < nk * nk; c += NT) {
+    const int kzi = int(__umulhi(unsigned(c), inv)), kyi = c - kzi * nk;
+    cplx<T>* b = a + kzi * R + kyi;
+    cplx<T> v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = b[k * pstride];
+    Fft<T, S, D>::run(v);
+#pragma unroll
+    for (int k = 0; k < D; ++k) b[k * pstride] = v[k];
+  }
+}
+
+template <class T, int S, int N, int NT = kThreads>
+__device__ inline void column_fft_rows_tile(cplx<T>* a, int d, int nk, int R, int pstride) {
+  if constexpr (N % 12 == 0) if (d == 12) return column_fft_rows<T, S, 12, NT>(a, nk, R, pstride);
+  if constexpr (N % 10 == 0) if (d == 10) return column_fft_rows<T, S, 10, NT>(a, nk, R, pstride);
+  if constexpr (N % 9 == 0) if (d == 9) return column_fft_rows<T, S, 9, NT>(a, nk, R, pstride);
+  if constexpr (N % 8 == 0) if (d == 8) return column_fft_rows<T, S, 8, NT>(a, nk, R, pstride);
+  if constexpr (N % 6 == 0) if (d == 6) return column_fft_rows<T, S, 6, NT>(a, nk, R, pstride);
+  if constexpr (N % 5 == 0) if (d == 5) return column_fft_rows<T, S, 5, NT>(a, nk, R, pstride);
+  if constexpr (N % 4 == 0) if (d == 4) return column_fft_rows<T, S, 4, NT>(a, nk, R, pstride);
+  if constexpr (N % 3 == 0) if (d == 3) return column_fft_rows<T, S, 3, NT>(a, nk, R, pstride);
+  if constexpr (N % 2 == 0) if (d == 2) return column_fft_rows<T, S, 2, NT>(a, nk, R, pstride);
+}
+
 // Forward pruned transform of NF fields.  Load(f, x, y, z) returns the
 // field value; acc[f][t] accumulates output o = threadIdx.x + t * NT
 // (o < nout; NT threads per workgroup) whose packed descriptor is gdesc[t]
@@ -123,26 +172,28 @@ __device__ inline void column_fft_tile(cplx<T>* a, int d, int nc) {
 // group, a length-sx FFT across its planes gives, for every kept (ky, kz),
 // Y_x2(q) = sum_xs f(x2 + M xs) w_sx^{q xs}; output kx then needs only
 // w_N^{kx x2} Y_x2(kx mod sx), one product per group instead of sx.
-// KM >= 0 fixes kmax = KM at compile time (see kwin).
+// KM >= 0 fixes kmax = KM at compile time (see kwin).  L is the forward
+// layout (fwd_lds).
 template <class T, int S, int N, int NF, int OPT, int NT = kThreads, int KM = -1, class Load>
-__device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax_rt, int sx,
-                                      const int (&gdesc)[OPT], int nout,
-                                      cplx<T> (&acc)[NF][OPT], const SlabLds<T>& L) {
+__device__ __forceinline__ void forward_pruned(const Load& ld, int nf_active, int kmax_rt, int sx,
+                                               const int (&gdesc)[OPT], int nout,
+                                               cplx<T> (&acc)[NF][OPT], const SlabLds<T>& L) {
+  constexpr int R = slab_row(N);
   const int kmax = KM >= 0 ? KM : kmax_rt;
-  const int nk = 2 * kmax + 1, nc = nk * nk, M = N / sx;
+  const int nk = 2 * kmax + 1, M = N / sx, pstride = nk * R;
   const int tid = threadIdx.x;
-  // per output: t2 offset of its residue column (low 24 bits) and kx mod N
+  // per output: offset of its (residue plane, kz, ky) entry (low 24 bits) and kx
   int ox[OPT];
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
     const int kxm = gdesc[t] & 0xff, kyi = (gdesc[t] >> 8) & 0xff, kzi = gdesc[t] >> 16;
-    ox[t] = (((kxm % sx) * nk + kyi) * nk + kzi) | (kxm << 24);
+    ox[t] = ((kxm % sx) * pstride + kzi * R + kyi) | (kxm << 24);
   }
   for (int x2 = 0; x2 < M; ++x2) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       if (f >= nf_active) break;
-      // z pass: line (xs, y)
+      // z pass: line (xs, y) -> rows (xs, kz)
       for (int l = tid; l < sx * N; l += NT) {
         const int xs = l / N, y = l - xs * N, x = x2 + M * xs;
         cplx<T> v[N];
@@ -152,39 +203,36 @@ __device__ inline void forward_pruned(const Load& ld, int nf_active, int kmax_rt
 #pragma unroll
         for (int z = 0; z < N; ++z) {
           const int kz = (z <= N / 2) ? z : z - N;
-          if (kz >= -kmax && kz <= kmax) L.t1[(xs * nk + kz + kmax) * slab_row(N) + y] = v[z];
+          if (kz >= -kmax && kz <= kmax) L.t1[(xs * nk + kz + kmax) * R + y] = v[z];
         }
       }
       __syncthreads();
-      // y pass: line (xs, kz)
+      // y pass: row (xs, kz) in place; the kept ky land at the row's start
       for (int l = tid; l < sx * nk; l += NT) {
-        const int xs = l / nk, kzi = l - xs * nk;
+        cplx<T>* row = L.t1 + l * R;
         cplx<T> v[N];
-        const cplx<T>* src = L.t1 + (xs * nk + kzi) * slab_row(N);
 #pragma unroll
-        for (int y = 0; y < N; ++y) v[y] = src[y];
+        for (int y = 0; y < N; ++y) v[y] = row[y];
         Fft<T, S, N>::run(v);
 #pragma unroll
         for (int y = 0; y < N; ++y) {
           const int ky = (y <= N / 2) ? y : y - N;
-          if (ky >= -kmax && ky <= kmax) L.t2[(xs * nk + ky + kmax) * nk + kzi] = v[y];
+          if (ky >= -kmax && ky <= kmax) row[ky + kmax] = v[y];
         }
       }
       __syncthreads();
       // x: length-sx FFT across the group's planes, then one product per output
-      column_fft_tile<T, S, N, NT>(L.t2, sx, nc);
+      column_fft_rows_tile<T, S, N, NT>(L.t1, sx, nk, R, pstride);
       if (sx > 1) __syncthreads();
 #pragma unroll
       for (int t = 0; t < OPT; ++t) {
         const int o = tid + t * NT;
         if (o < nout)
-          acc[f][t] = cfma(L.tw[((ox[t] >> 24) * x2) % N], L.t2[ox[t] & 0xffffff], acc[f][t]);
+          acc[f][t] = cfma(L.tw[((ox[t] >> 24) * x2) % N], L.t1[ox[t] & 0xffffff], acc[f][t]);
       }
-      // no barrier here: the next z pass writes only t1, and t2 is rewritten
-      // only after the barrier that follows it
+      __syncthreads();  // the next z pass overwrites the rows
     }
   }
-  __syncthreads();
 }
 
 // Inverse transform of NF coefficient vectors given on a sphere whose
