@@ -82,10 +82,12 @@ def workload(name):
     return {"c1": C1, "c2": C2, "c3": C3}[name]
 
 
-def stage_work(info, n, stage):
-    """Algorithmic (flops, bytes) of one energy for a timing stage."""
+def stage_work(info, n, stage, prec="fp64"):
+    """Algorithmic (flops, bytes) of one energy for a timing stage (N_r: the
+    internal transform grid)."""
     nr, ng, nh, no, nv, npw, nt = (info.n_r, info.n_g, info.n_h, info.n_occ, info.n_vir,
                                    info.n_pw, info.n_tau)
+    es = 8 if prec == "fp64" else 4
     lg = math.log2(nr)
     if stage == "chi_tiles":      # symmetric real GEMMs, upper triangle only
         return nt * nr * nr * (no + nv) * 1.0, None
@@ -93,13 +95,41 @@ def stage_work(info, n, stage):
         return nt * 4.0 * nh * no * nv * npw, None
     if stage == "pair":           # N_o^2 complex 3-D FFTs per outer G' (H and -H)
         return nt * ng * no * no * 5.0 * nr * lg / 2.0 * 1.0, None
-    if stage == "chi_rows":       # read chi rows once
-        return None, nt * 8.0 * nr * nr
-    if stage == "chi_cols":
-        return None, nt * 16.0 * nh * nr
+    if stage == "chi_rows":       # read the real chi rows once
+        return None, nt * es * nr * nr
+    if stage == "chi_cols":       # read chi(r, G') once
+        return None, nt * 2 * es * nh * nr
     if stage == "w_synth":
         return nt * nh * no * 5.0 * nr * lg, None
     return None, None
+
+
+def stage_roofline(stage, ms_tot, launches, steps, prec, work):
+    """Achieved rate of one stage against its MI355X peak.  GEMM stages are
+    matrix-core bound: in the BF16x3 form each algorithmic flop costs three
+    BF16 MFMA flops, so mfma_frac = 3 x achieved / 2.5 PFLOP/s."""
+    flops, byts = work
+    per_launch_s = ms_tot / 1000.0 / max(launches, 1)
+    if per_launch_s <= 0:
+        return None
+    if flops is not None:
+        ach = flops * steps / max(launches, 1) / per_launch_s
+        if stage in ("pair", "w_synth"):
+            peak, bound = (PEAK_FP64 if prec == "fp64" else PEAK_FP32), "alu"
+            roof = {"bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / peak}
+        else:
+            peak = {"fp64": PEAK_FP64, "fp32": PEAK_FP32, "bf16x3": PEAK_BF16}[prec]
+            mult = 3.0 if prec == "bf16x3" else 1.0
+            roof = {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / peak, "mfma_frac": mult * ach / peak}
+    else:
+        ach = byts * steps / max(launches, 1) / per_launch_s
+        roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": ach / PEAK_HBM}
+    roof["launches_per_step"] = launches / steps
+    roof["mean_launch_ms"] = 1000.0 * per_launch_s
+    return roof
 
 
 def cpu_baseline(spec, m, e, c, budget_s=25.0):
@@ -136,27 +166,20 @@ def roofline(timing, work_of, steps, prec):
     """Roofline entry of the dominant stage: work_of(stage) -> (flops, bytes) per step."""
     dom = max(timing, key=lambda k: timing[k][0])
     ms_tot, launches = timing[dom]
-    flops, byts = work_of(dom)
-    per_launch_s = ms_tot / 1000.0 / max(launches, 1)
-    if flops is not None:
-        ach = flops * steps / max(launches, 1) / per_launch_s
-        if dom in ("pair", "w_synth"):
-            peak, bound = (PEAK_FP64 if prec == "fp64" else PEAK_FP32), "alu"
-        else:
-            peak = {"fp64": PEAK_FP64, "fp32": PEAK_FP32, "bf16x3": PEAK_BF16}[prec]
-            if dom == "w_gemm" and prec == "bf16x3":
-                peak = PEAK_FP32
-            bound = "mfma"
-        roof = {"bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None}
-    else:
-        ach = byts * steps / max(launches, 1) / per_launch_s
-        roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": ach / PEAK_HBM, "traffic": None}
+    roof = stage_roofline(dom, ms_tot, launches, steps, prec, work_of(dom))
+    roof = {"bound": roof.pop("bound"), "achieved": roof.pop("achieved"), "peak": roof.pop("peak"),
+            "unit": roof.pop("unit"), "frac": roof.pop("frac"), "traffic": None, **roof}
     roof["kernel"] = dom
-    roof["launches_per_step"] = launches / steps
-    roof["mean_launch_ms"] = 1000.0 * per_launch_s
     return roof
+
+
+def all_stage_rooflines(timing, work_of, steps, prec):
+    out = {}
+    for st, (ms_tot, launches) in timing.items():
+        w = work_of(st)
+        if launches and (w[0] is not None or w[1] is not None):
+            out[st] = stage_roofline(st, ms_tot, launches, steps, prec, w)
+    return out
 
 
 def bench_batch(args):
@@ -209,12 +232,13 @@ def bench_batch(args):
     def work_of(stage):
         fl, by = 0.0, 0.0
         for inf, s in zip(infos, specs):
-            f1, b1 = stage_work(inf, s.n, stage)
+            f1, b1 = stage_work(inf, s.n, stage, args.prec)
             fl = fl + f1 if f1 is not None else None
             by = by + b1 if b1 is not None else None
         return (fl if fl else None), (by if by else None)
 
     roof = roofline(timing, work_of, 1, args.prec)
+    stage_roofs = all_stage_rooflines(timing, work_of, 1, args.prec)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)...")
@@ -235,7 +259,8 @@ def bench_batch(args):
                       "timed_pass_max_diff": float(max(np.abs(ed_t - ed).max(),
                                                        np.abs(ex_t - ex).max()))},
            "stage_ms_eager_pass": {k: v[0] for k, v in timing.items()},
-           "setup_s": t_setup, "roofline": roof, "cpu_baseline": cpu}
+           "setup_s": t_setup, "roofline": roof, "stage_roofline": stage_roofs,
+           "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 
@@ -345,7 +370,9 @@ def main():
             f"dE_d {ed - ed64:.2e} dE_x {ex - ex64:.2e}")
 
     # dominant kernel stage and its roofline
-    roof = roofline(timing, lambda st: stage_work(info, spec.n, st), args.steps, args.prec)
+    work_of = lambda st: stage_work(info, spec.n, st, args.prec)  # noqa: E731
+    roof = roofline(timing, work_of, args.steps, args.prec)
+    stage_roofs = all_stage_rooflines(timing, work_of, args.steps, args.prec)
     tr = load_traffic(args.config, args.prec, roof["kernel"])
     if tr is not None:
         roof["traffic"] = tr["bytes_per_launch"]
@@ -370,7 +397,7 @@ def main():
            "energy": {"e_direct": ed, "e_exchange": ex, "quad_delta": qe},
            "stage_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
            "setup_s": t_setup, "fp64_reference": ref,
-           "roofline": roof, "cpu_baseline": cpu}
+           "roofline": roof, "stage_roofline": stage_roofs, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     ctx.close()
 

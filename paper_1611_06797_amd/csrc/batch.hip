@@ -225,7 +225,7 @@ ltmp2_status tune_group(ltmp2_batch* b, Group& g) {
   double best = 1e300;
   int bsx = smax, bwg = 2;
   for (int sx : sxs)
-    for (int wg : {1, 2, 4}) {
+    for (int wg : {1, 2, 3, 4}) {
       if ((s = pair_launch(b, g, r0, sx, wg))) break;  // warm-up of this variant
       (void)hipEventRecord(e0, b->stream);
       if ((s = pair_launch(b, g, r0, sx, wg))) break;
@@ -304,7 +304,7 @@ extern "C" ltmp2_status ltmp2_batch_create(int n_cells, const ltmp2_params* para
   // groups by grid size; rounds so one group's transformed states fit the budget
   std::map<int, std::vector<int>> byn;
   for (int k = 0; k < n_cells; ++k) byn[b->cells[k]->n].push_back(k);
-  const size_t budget = size_t(48) << 30;  // transformed states of one group
+  const size_t budget = size_t(16) << 30;  // transformed states of one group
   size_t es = b->cells[0]->esz, chi_b = 0, chihat_b = 0, P_b = 0, w_b = 0;
   for (auto& kv : byn) {
     Group g;
