@@ -17,11 +17,12 @@ namespace {
 constexpr int N = LTMP2_N;
 constexpr size_t kLdsCap = 150 * 1024;
 constexpr size_t kLdsHalf = 78 * 1024;
+constexpr size_t kLdsQuarter = 39 * 1024;
 
 template <class T>
 int choose_sx(int nk, int cap = 10) {
   int sx = slab_tile_at_most(N, cap);
-  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) > kLdsCap) sx = slab_tile_at_most(N, sx - 1);
+  while (sx > 1 && inv_lds_bytes<T>(N, nk, sx) > kLdsCap) sx = slab_tile_at_most(N, sx - 1);
   return sx;
 }
 
@@ -82,7 +83,7 @@ template <class T>
 ltmp2_status orbitals(const cplx<double>* coef, int nstates, int npw, SphereCols sc, double scale,
                       T* psi, long ld, hipStream_t st) {
   const int nk = 2 * sc.kmax + 1, sx = choose_sx<T>(nk);
-  return launch(k_orbitals<T, N>, dim3(nstates), slab_lds_bytes<T>(N, nk, sx), st, coef, npw, sc,
+  return launch(k_orbitals<T, N>, dim3(nstates), inv_lds_bytes<T>(N, nk, sx), st, coef, npw, sc,
                 sx, scale, psi, ld);
 }
 
@@ -149,11 +150,17 @@ ltmp2_status chi_cols(const cplx<T>* chihat, long ld, const int* gdesc, int ng, 
 template <class T>
 ltmp2_status wstates(const T* P, int npw, const int* wq, const signed char* wsgn, SphereCols sc,
                      int nitems, double scale, cplx<T>* w, long ld, hipStream_t st) {
-  // at most half the CU's shared memory, so that two workgroups fit
+  // the largest slab tile that lets four workgroups share a CU, unless two
+  // workgroups per CU would allow more than twice that tile
   const int nk = 2 * sc.kmax + 1;
-  int sx = slab_tile_at_most(N, 10);
-  while (sx > 1 && slab_lds_bytes<T>(N, nk, sx) > kLdsHalf) sx = slab_tile_at_most(N, sx - 1);
-  const size_t lds = slab_lds_bytes<T>(N, nk, sx);
+  auto tile = [nk](size_t cap) {
+    int sx = slab_tile_at_most(N, 10);
+    while (sx > 1 && inv_lds_bytes<T>(N, nk, sx) > cap) sx = slab_tile_at_most(N, sx - 1);
+    return sx;
+  };
+  const int s4 = tile(kLdsQuarter), s2 = tile(kLdsHalf);
+  const int sx = 2 * s4 >= s2 ? s4 : s2;
+  const size_t lds = inv_lds_bytes<T>(N, nk, sx);
   // orbital spheres at the alias-free window and one below run kernels
   // compiled for that kmax (no per-element branches in the y and z stages)
   constexpr int ko = korb_win(N);

@@ -23,10 +23,8 @@ __global__ __launch_bounds__(kThreads) void k_orbitals(const cplx<double>* __res
                                                        T* __restrict__ psi, long ld) {
   extern __shared__ __align__(16) char smem[];
   const int nk = 2 * sc.kmax + 1;
-  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  SlabLds<T> L = inv_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, 1, N>(L.tw);
-  for (int e = threadIdx.x; e < sx * nk * nk; e += kThreads) L.t2[e] = {T(0), T(0)};
-  __syncthreads();
   const long p = blockIdx.x;
   const cplx<double>* c = coef + p * npw;
   T* out = psi + p * ld;
@@ -188,10 +186,8 @@ __global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, i
                                                       cplx<T>* __restrict__ w, long ld) {
   extern __shared__ __align__(16) char smem[];
   const int nk = 2 * (KO >= 0 ? KO : sc.kmax) + 1;
-  SlabLds<T> L = slab_lds<T>(smem, N, nk, sx);
+  SlabLds<T> L = inv_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, 1, N>(L.tw);
-  for (int e = threadIdx.x; e < sx * nk * nk; e += kThreads) L.t2[e] = {T(0), T(0)};
-  __syncthreads();
   const long item = blockIdx.x;
   const T* pre = P + (2 * item) * long(npw);
   const T* pim = pre + npw;

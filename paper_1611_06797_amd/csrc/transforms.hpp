@@ -37,27 +37,15 @@ __host__ __device__ constexpr int slab_row(int n) { return n + (n % 2 == 0 ? 1 :
 template <class T>
 struct SlabLds {
   cplx<T>* t1;  // [SX][nk][slab_row(n)]
-  cplx<T>* t2;  // [SX][nk][nk]
   cplx<T>* tw;  // [n]
+  int* cmap;    // inverse transforms: [nk][nk] sphere column of each (kz, ky) slot, or -1
 };
 
-template <class T>
-__host__ __device__ inline size_t slab_lds_bytes(int n, int nk, int sx) {
-  return sizeof(cplx<T>) * (size_t(sx) * nk * slab_row(n) + size_t(sx) * nk * nk + n);
-}
-
-template <class T>
-__device__ inline SlabLds<T> slab_lds(void* base, int n, int nk, int sx) {
-  SlabLds<T> s;
-  s.t1 = reinterpret_cast<cplx<T>*>(base);
-  s.t2 = s.t1 + size_t(sx) * nk * slab_row(n);
-  s.tw = s.t2 + size_t(sx) * nk * nk;
-  return s;
-}
-
-// Forward transforms keep everything in the z-pass buffer: the y pass
-// writes its kept outputs back into the row it read, so the layout is
-// t1 [SX][nk][slab_row(n)] followed by the twiddles.
+// Both transform directions keep a slab group in one buffer,
+// t1 [SX][nk][slab_row(n)], followed by the twiddles.  Forward: the z pass
+// fills rows (xs, kz), the y pass writes its kept outputs back into the
+// start of the row it read.  Inverse: the x stage fills the start of each
+// row (kept ky), the y stage expands the row in place to all n values of y.
 template <class T>
 __host__ __device__ inline size_t fwd_lds_bytes(int n, int nk, int sx) {
   return sizeof(cplx<T>) * (size_t(sx) * nk * slab_row(n) + n);
@@ -67,8 +55,21 @@ template <class T>
 __device__ inline SlabLds<T> fwd_lds(void* base, int n, int nk, int sx) {
   SlabLds<T> s;
   s.t1 = reinterpret_cast<cplx<T>*>(base);
-  s.t2 = nullptr;
   s.tw = s.t1 + size_t(sx) * nk * slab_row(n);
+  s.cmap = nullptr;
+  return s;
+}
+
+// The inverse layout adds the slot-to-column map after the twiddles.
+template <class T>
+__host__ __device__ inline size_t inv_lds_bytes(int n, int nk, int sx) {
+  return fwd_lds_bytes<T>(n, nk, sx) + sizeof(int) * size_t(nk) * nk;
+}
+
+template <class T>
+__device__ inline SlabLds<T> inv_lds(void* base, int n, int nk, int sx) {
+  SlabLds<T> s = fwd_lds<T>(base, n, nk, sx);
+  s.cmap = reinterpret_cast<int*>(s.tw + n);
   return s;
 }
 
@@ -240,58 +241,67 @@ __device__ __forceinline__ void forward_pruned(const Load& ld, int nf_active, in
 // [cstart[c], cstart[c+1]) with packed (ky + kmax) | (kz + kmax) << 8 in
 // cdesc[c] and consecutive, ascending kx values ckx[e].  Coef(f, e) returns
 // entry e of item f; Store(f, x, y, z, v) receives the synthesised grid
-// value.  t2 must be zeroed once by the caller (entries outside the columns
-// stay zero).
+// value.  L is the inverse layout (inv_lds) with its twiddles filled; the
+// first barrier inside orders them before their use.
 //
 // The x transform uses the same split as the forward one (sx divides N,
-// group x2 = planes x2 + M xs): per column and residue q < sx,
-// Z(q) = sum_{kx = q mod sx} c(kx) w_N^{kx x2}, then a length-sx FFT over q
-// gives the group's planes.
+// group x2 = planes x2 + M xs): per (ky, kz) slot and residue q < sx,
+// Z(q) = sum_{kx = q mod sx} c(kx) w_N^{kx x2} (zero for slots outside the
+// sphere), then a length-sx FFT over q gives the group's planes.
 // KO >= 0 fixes kmax = KO at compile time (see korb_win).
 template <class T, int N, int NF, int KO = -1, class Coef, class Store>
 __device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_active,
                                       int kmax_rt, int sx, int ncol, const int* cdesc,
                                       const int* cstart, const int* ckx, const SlabLds<T>& L) {
+  constexpr int R = slab_row(N);
   const int kmax = KO >= 0 ? KO : kmax_rt;
   const int nk = 2 * kmax + 1, nc = nk * nk, M = N / sx;
   const int tid = threadIdx.x;
+  for (int s = tid; s < nc; s += kThreads) L.cmap[s] = -1;
+  __syncthreads();
+  for (int c = tid; c < ncol; c += kThreads) {
+    const int d = cdesc[c];
+    L.cmap[(d >> 8) * nk + (d & 0xff)] = c;
+  }
+  __syncthreads();
   for (int x2 = 0; x2 < M; ++x2) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       if (f >= nf_active) break;
-      // x stage: residue sums for each column
-      for (int l = tid; l < sx * ncol; l += kThreads) {
-        const int q = l / ncol, c = l - q * ncol;
-        const int e0 = cstart[c], e1 = cstart[c + 1];
-        int kxm = ckx[e0] % N;
-        if (kxm < 0) kxm += N;
-        const int skip = (q - kxm % sx + sx) % sx;
-        kxm += skip;
+      // x stage: residue sums for every slot s = kzi * nk + kyi
+      for (int l = tid; l < sx * nc; l += kThreads) {
+        const int q = l / nc, sl = l - q * nc;
+        const int c = L.cmap[sl];
         cplx<T> s = {T(0), T(0)};
-        for (int e = e0 + skip; e < e1; e += sx) {
-          s = cfma(cf(f, e), L.tw[(kxm * x2) % N], s);
-          kxm += sx;
+        if (c >= 0) {
+          const int e0 = cstart[c], e1 = cstart[c + 1];
+          int kxm = ckx[e0] % N;
+          if (kxm < 0) kxm += N;
+          const int skip = (q - kxm % sx + sx) % sx;
+          kxm += skip;
+          for (int e = e0 + skip; e < e1; e += sx) {
+            s = cfma(cf(f, e), L.tw[(kxm * x2) % N], s);
+            kxm += sx;
+          }
         }
-        const int d = cdesc[c];
-        L.t2[(q * nk + (d & 0xff)) * nk + (d >> 8)] = s;
+        const int kzi = sl / nk;
+        L.t1[(q * nk + kzi) * R + (sl - kzi * nk)] = s;
       }
       __syncthreads();
-      column_fft_tile<T, 1, N>(L.t2, sx, nc);
+      column_fft_rows_tile<T, 1, N>(L.t1, sx, nk, R, nk * R);
       if (sx > 1) __syncthreads();
-      // y stage: line (xs, kz)
+      // y stage: line (xs, kz), expanded in place from nk to N values
       for (int l = tid; l < sx * nk; l += kThreads) {
-        const int xs = l / nk, kzi = l - xs * nk;
+        cplx<T>* row = L.t1 + l * R;
         cplx<T> v[N];
 #pragma unroll
         for (int y = 0; y < N; ++y) {
           const int ky = (y <= N / 2) ? y : y - N;
-          v[y] = (ky >= -kmax && ky <= kmax) ? L.t2[(xs * nk + ky + kmax) * nk + kzi]
-                                             : cplx<T>{T(0), T(0)};
+          v[y] = (ky >= -kmax && ky <= kmax) ? row[ky + kmax] : cplx<T>{T(0), T(0)};
         }
         Fft<T, 1, N>::run(v);
-        cplx<T>* dst = L.t1 + (xs * nk + kzi) * slab_row(N);
 #pragma unroll
-        for (int y = 0; y < N; ++y) dst[y] = v[y];
+        for (int y = 0; y < N; ++y) row[y] = v[y];
       }
       __syncthreads();
       // z stage: line (xs, y)
@@ -301,18 +311,16 @@ __device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_ac
 #pragma unroll
         for (int z = 0; z < N; ++z) {
           const int kz = (z <= N / 2) ? z : z - N;
-          v[z] = (kz >= -kmax && kz <= kmax) ? L.t1[(xs * nk + kz + kmax) * slab_row(N) + y]
+          v[z] = (kz >= -kmax && kz <= kmax) ? L.t1[(xs * nk + kz + kmax) * R + y]
                                              : cplx<T>{T(0), T(0)};
         }
         Fft<T, 1, N>::run(v);
 #pragma unroll
         for (int z = 0; z < N; ++z) st(f, x, y, z, v[z]);
       }
-      // no barrier here: the next x stage writes only t2, and t1 is rewritten
-      // only after the barriers that follow it
+      __syncthreads();  // the next x stage overwrites the rows
     }
   }
-  __syncthreads();
 }
 
 // Block-wide sum of a double (deterministic order), result valid in thread 0.

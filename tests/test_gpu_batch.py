@@ -68,7 +68,7 @@ def test_batch_fp64_matches_oracle(mix):
     assert [g["n_fft"] for g in groups] == [12, 15]
     assert [g["n_cells"] for g in groups] == [5, 1]
     for g in groups:
-        assert g["slab_tile"] >= 1 and g["wg_per_cu"] in (1, 2, 4)
+        assert g["slab_tile"] >= 1 and g["wg_per_cu"] in (1, 2, 3, 4)
     for k, it in enumerate(mix):
         r = it["ref"]
         tol = it["spec"].n_occ * 1e-6
