@@ -7,10 +7,11 @@
 // FP32 (the lo*lo term is below the FP32 rounding of the sum; Henry, Tang,
 // Heinecke, ARITH 2019).
 //
-// Per K-slice of 64 the workgroup stages the four split operand tiles in
-// shared memory ([128][64 + 8] bf16 each, k-contiguous per row) with 16-byte
-// loads and stores, and fetches the next slice into registers while the
-// matrix cores work.  Four waves each own a 64 x 64 quarter of the tile
+// Per K-slice of 32 the workgroup stages the four split operand tiles in
+// shared memory ([128][32 + 8] bf16 each, k-contiguous per row) with 16-byte
+// loads and stores, in two alternating buffers: while the matrix cores work
+// on one slice, the next is fetched into registers and stored into the other
+// buffer (one barrier per slice).  Four waves each own a 64 x 64 quarter of the tile
 // (4 x 4 blocks of 16 x 16); accumulator element v of lane l of a block is
 // D[4 (l / 16) + v][l % 16].  Tiles are assigned so that the workgroups
 // resident on one XCD (dispatch is round-robin over the 8 XCDs) share their
@@ -26,7 +27,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int T3 = 128, T3_K = 64, T3_KP = 72;
+constexpr int T3 = 128, T3_K = 32, T3_KP = 40;
 
 struct Split3Tile {
   __bf16 ah[T3][T3_KP], al[T3][T3_KP], bh[T3][T3_KP], bl[T3][T3_KP];
@@ -68,31 +69,25 @@ __global__ __launch_bounds__(256) void k_split3(const float* __restrict__ src, l
   *reinterpret_cast<bf16x8*>(lo + d) = vl;
 }
 
-// Thread t fetches k-octets oct + (t / 64) and oct + 4 + (t / 64), rows
-// m0 + (t % 64) and m0 + 64 + (t % 64), hi and lo (8 x 16 bytes).
-__device__ __forceinline__ void m3_fetch(const Op3& a, long m0, long oct, u32x4 (&r)[8]) {
+// Thread t fetches k-octet oct + (t / 64), rows m0 + (t % 64) and
+// m0 + 64 + (t % 64), hi and lo (4 x 16 bytes).
+__device__ __forceinline__ void m3_fetch(const Op3& a, long m0, long oct, u32x4 (&r)[4]) {
   const int o = threadIdx.x >> 6, mm = threadIdx.x & 63;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const long base = ((oct + o + 4 * h) * a.ld + m0 + mm) * 8;
-    r[4 * h + 0] = *reinterpret_cast<const u32x4*>(a.hi + base);
-    r[4 * h + 1] = *reinterpret_cast<const u32x4*>(a.hi + base + 64 * 8);
-    r[4 * h + 2] = *reinterpret_cast<const u32x4*>(a.lo + base);
-    r[4 * h + 3] = *reinterpret_cast<const u32x4*>(a.lo + base + 64 * 8);
-  }
+  const long base = ((oct + o) * a.ld + m0 + mm) * 8;
+  r[0] = *reinterpret_cast<const u32x4*>(a.hi + base);
+  r[1] = *reinterpret_cast<const u32x4*>(a.hi + base + 64 * 8);
+  r[2] = *reinterpret_cast<const u32x4*>(a.lo + base);
+  r[3] = *reinterpret_cast<const u32x4*>(a.lo + base + 64 * 8);
 }
 
 __device__ __forceinline__ void m3_store(__bf16 (*hi)[T3_KP], __bf16 (*lo)[T3_KP],
-                                         const u32x4 (&r)[8]) {
+                                         const u32x4 (&r)[4]) {
   const int o = threadIdx.x >> 6, mm = threadIdx.x & 63;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int kc = 8 * (o + 4 * h);
-    *reinterpret_cast<u32x4*>(&hi[mm][kc]) = r[4 * h + 0];
-    *reinterpret_cast<u32x4*>(&hi[mm + 64][kc]) = r[4 * h + 1];
-    *reinterpret_cast<u32x4*>(&lo[mm][kc]) = r[4 * h + 2];
-    *reinterpret_cast<u32x4*>(&lo[mm + 64][kc]) = r[4 * h + 3];
-  }
+  const int kc = 8 * o;
+  *reinterpret_cast<u32x4*>(&hi[mm][kc]) = r[0];
+  *reinterpret_cast<u32x4*>(&hi[mm + 64][kc]) = r[1];
+  *reinterpret_cast<u32x4*>(&lo[mm][kc]) = r[2];
+  *reinterpret_cast<u32x4*>(&lo[mm + 64][kc]) = r[3];
 }
 
 __device__ __forceinline__ void m3_mma(const Split3Tile& s, f32x4 (&acc)[4][4]) {
@@ -122,24 +117,33 @@ __device__ __forceinline__ void m3_mma(const Split3Tile& s, f32x4 (&acc)[4][4]) 
 }
 
 // acc += sum over k-octets [oa, oa + Kpad / 8) of A and [ob, ...) of B on the
-// tile rows m0 .. m0 + 127 of A and n0 .. n0 + 127 of B (Kpad a multiple of 64).
+// tile rows m0 .. m0 + 127 of A and n0 .. n0 + 127 of B (Kpad a multiple of
+// 32).  Ends with a barrier, so the buffers may be refilled at once.
 __device__ __forceinline__ void m3_phase(const Op3& A, long m0, long oa, const Op3& B, long n0,
-                                         long ob, int Kpad, Split3Tile& s, f32x4 (&acc)[4][4]) {
+                                         long ob, int Kpad, Split3Tile (&s)[2],
+                                         f32x4 (&acc)[4][4]) {
+  constexpr int OCT = T3_K / 8;
   const int nks = Kpad / T3_K;
-  u32x4 ra[8], rb[8];
-  if (nks > 0) {
-    m3_fetch(A, m0, oa, ra);
-    m3_fetch(B, n0, ob, rb);
-  }
+  if (nks <= 0) return;
+  u32x4 ra[4], rb[4];
+  m3_fetch(A, m0, oa, ra);
+  m3_fetch(B, n0, ob, rb);
+  m3_store(s[0].ah, s[0].al, ra);
+  m3_store(s[0].bh, s[0].bl, rb);
+  __syncthreads();
   for (int ks = 0; ks < nks; ++ks) {
-    m3_store(s.ah, s.al, ra);
-    m3_store(s.bh, s.bl, rb);
-    __syncthreads();
-    if (ks + 1 < nks) {
-      m3_fetch(A, m0, oa + 8 * (ks + 1), ra);
-      m3_fetch(B, n0, ob + 8 * (ks + 1), rb);
+    const bool more = ks + 1 < nks;
+    if (more) {
+      m3_fetch(A, m0, oa + OCT * (ks + 1), ra);
+      m3_fetch(B, n0, ob + OCT * (ks + 1), rb);
     }
-    m3_mma(s, acc);
+    m3_mma(s[ks & 1], acc);
+    if (more) {
+      // buffer (ks + 1) & 1 was last read in slice ks - 1, before the barrier
+      Split3Tile& d = s[(ks + 1) & 1];
+      m3_store(d.ah, d.al, ra);
+      m3_store(d.bh, d.bl, rb);
+    }
     __syncthreads();
   }
 }
@@ -159,7 +163,7 @@ __device__ __forceinline__ void m3_zero(f32x4 (&acc)[4][4]) {
 // on one XCD.  Off-diagonal tiles are also written transposed.
 __global__ __launch_bounds__(256, 2) void k_chi3(Op3 psi, int kpo, int kpv, int t,
                                                 float* __restrict__ chi, long ldc) {
-  __shared__ Split3Tile s;
+  __shared__ Split3Tile s[2];
   const int ts = (t + 7) / 8;
   const long nsuper = long(ts) * (ts + 1) / 2;
   const long b = blockIdx.x;
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(256, 2) void k_mm3(Op3 A, long am0, Op3 B, float* _
                                                long ldc, int M, int N, int Kpad,
                                                const double* __restrict__ rowscale, int rdiv,
                                                int rmod) {
-  __shared__ Split3Tile s;
+  __shared__ Split3Tile s[2];
   const int tn = (N + T3 - 1) / T3;
   const long total = long((M + T3 - 1) / T3) * tn;
   const long per = (total + 7) / 8;
