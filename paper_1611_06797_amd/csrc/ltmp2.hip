@@ -502,6 +502,9 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
   }
   c->gblock = (int)std::max<size_t>(1, std::min<size_t>(c->nh, budget / per_g));
 
+  // the inverse transforms pack a column's first entry into 16 bits
+  if (ckx.size() >= 65536)
+    return fail(nullptr, LTMP2_EINVAL, "orbital sphere above 65535 plane waves");
   // device allocations and uploads
   ltmp2_status s;
   if ((s = upload(c, &c->d_cdesc, cdesc)) || (s = upload(c, &c->d_cstart, cstart)) ||

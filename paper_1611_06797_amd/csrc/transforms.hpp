@@ -38,7 +38,7 @@ template <class T>
 struct SlabLds {
   cplx<T>* t1;  // [SX][nk][slab_row(n)]
   cplx<T>* tw;  // [n]
-  int* cmap;    // inverse transforms: [nk][nk] sphere column of each (kz, ky) slot, or -1
+  int* cmap;    // inverse transforms: [nk][nk] packed sphere column of each (kz, ky) slot
 };
 
 // Both transform directions keep a slab group in one buffer,
@@ -60,7 +60,10 @@ __device__ inline SlabLds<T> fwd_lds(void* base, int n, int nk, int sx) {
   return s;
 }
 
-// The inverse layout adds the slot-to-column map after the twiddles.
+// The inverse layout adds the slot-to-column map after the twiddles: per
+// (kz, ky) slot, the column's first entry | its length << 16 | (kx of its
+// first entry mod n) << 22, or 0 outside the sphere (entries < 2^16, column
+// lengths and n < 64).
 template <class T>
 __host__ __device__ inline size_t inv_lds_bytes(int n, int nk, int sx) {
   return fwd_lds_bytes<T>(n, nk, sx) + sizeof(int) * size_t(nk) * nk;
@@ -242,7 +245,8 @@ __device__ __forceinline__ void forward_pruned(const Load& ld, int nf_active, in
 // cdesc[c] and consecutive, ascending kx values ckx[e].  Coef(f, e) returns
 // entry e of item f; Store(f, x, y, z, v) receives the synthesised grid
 // value.  L is the inverse layout (inv_lds) with its twiddles filled; the
-// first barrier inside orders them before their use.
+// first barrier inside orders them before their use.  Requires fewer than
+// 2^16 entries, and column lengths and N below 64.
 //
 // The x transform uses the same split as the forward one (sx divides N,
 // group x2 = planes x2 + M xs): per (ky, kz) slot and residue q < sx,
@@ -257,11 +261,13 @@ __device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_ac
   const int kmax = KO >= 0 ? KO : kmax_rt;
   const int nk = 2 * kmax + 1, nc = nk * nk, M = N / sx;
   const int tid = threadIdx.x;
-  for (int s = tid; s < nc; s += kThreads) L.cmap[s] = -1;
+  for (int s = tid; s < nc; s += kThreads) L.cmap[s] = 0;
   __syncthreads();
   for (int c = tid; c < ncol; c += kThreads) {
-    const int d = cdesc[c];
-    L.cmap[(d >> 8) * nk + (d & 0xff)] = c;
+    const int d = cdesc[c], e0 = cstart[c];
+    int kxm = ckx[e0] % N;
+    if (kxm < 0) kxm += N;
+    L.cmap[(d >> 8) * nk + (d & 0xff)] = e0 | ((cstart[c + 1] - e0) << 16) | (kxm << 22);
   }
   __syncthreads();
   for (int x2 = 0; x2 < M; ++x2) {
@@ -271,12 +277,11 @@ __device__ inline void inverse_sphere(const Coef& cf, const Store& st, int nf_ac
       // x stage: residue sums for every slot s = kzi * nk + kyi
       for (int l = tid; l < sx * nc; l += kThreads) {
         const int q = l / nc, sl = l - q * nc;
-        const int c = L.cmap[sl];
+        const int m = L.cmap[sl];
         cplx<T> s = {T(0), T(0)};
-        if (c >= 0) {
-          const int e0 = cstart[c], e1 = cstart[c + 1];
-          int kxm = ckx[e0] % N;
-          if (kxm < 0) kxm += N;
+        if (m != 0) {
+          const int e0 = m & 0xffff, e1 = e0 + ((m >> 16) & 63);
+          int kxm = (m >> 22) & 63;
           const int skip = (q - kxm % sx + sx) % sx;
           kxm += skip;
           for (int e = e0 + skip; e < e1; e += sx) {
