@@ -299,7 +299,7 @@ def main():
                     help="skip timing the plain FP64 form beside the headline form")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the LTMP2 path runs on one GPU (no sharded form is built); --gpus must be 1"}))
         sys.exit(2)
 
     if args.config == "c4":
