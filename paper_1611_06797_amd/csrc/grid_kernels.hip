@@ -68,6 +68,7 @@ ltmp2_status launch(K kern, dim3 grid, size_t lds, hipStream_t st, auto... args)
 // leave room for only one wave per SIMD.  (FP64 registers do not fit two
 // 512-thread waves per SIMD; FP64 keeps 256 threads.)
 constexpr int kWideNT = 512, kWideOpt = 9;
+constexpr int kNarrowNT = 192;
 
 template <template <int> class F>
 ltmp2_status by_opt(int nout, auto&&... a) {
@@ -270,6 +271,15 @@ ltmp2_status pair_multi(const PairCell* cells, const long* prefix, int ncells, i
       if (ng_max > kWideOpt * kWideNT || sx < 1 || N % sx != 0 || sx > 12) return LTMP2_EINVAL;
       return pair_multi_km<T, kWideNT, kWideOpt>(kfix, cells, prefix, ncells, kmax_max, sx,
                                                   nblocks, st);
+    }
+    // a slab group of 129..192 z lines: 192-thread workgroups, one line each
+    if (sx >= 1 && sx <= 10 && N % sx == 0 && sx * N > 128 && sx * N <= kNarrowNT &&
+        ng_max <= 9 * kNarrowNT) {
+      if (ng_max <= 3 * kNarrowNT)
+        return pair_multi_km<T, kNarrowNT, 3>(kfix, cells, prefix, ncells, kmax_max, sx, nblocks,
+                                              st);
+      return pair_multi_km<T, kNarrowNT, 9>(kfix, cells, prefix, ncells, kmax_max, sx, nblocks,
+                                            st);
     }
   }
   return by_opt<PairMultiF<T>::template F>(ng_max, kfix, cells, prefix, ncells, kmax_max, sx,
