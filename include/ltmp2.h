@@ -20,7 +20,10 @@
  *   - cubic cell of side L (bohr), Omega = L^3, FFT grid n^3, dV = Omega / n^3;
  *   - reciprocal vectors G = (2 pi / L) m with integer Miller indices m;
  *   - orbitals psi_p(r) = Omega^-1/2 sum_G c_p(G) e^{iG.r} must be real on the
- *     grid (Gamma point, time-reversal symmetry: c_p(-G) = conj c_p(G));
+ *     grid up to a phase per orbital (Gamma point, time-reversal symmetry:
+ *     c_p(-G) = e^{2 i theta_p} conj c_p(G)), or span with their degenerate
+ *     partners a time-reversal invariant block; setup brings them to real
+ *     form (ltmp2_real_orbitals);
  *   - auxiliary set: G != 0 with |G|^2 / 2 <= eaux, |m_d| < n / 2;
  *   - real-space index used by device outputs: r = (x * n + z) * n + y
  *     for grid point (x, y, z) (z varies before y).
@@ -106,14 +109,21 @@ typedef struct {
                             at the auxiliary wavevectors on it, so every energy
                             equals the n_fft-grid value to rounding.  Grid rows
                             of ltmp2_green are on this grid. */
+  int g_block;           /* outer G' of the half set per transformed-state
+                            block (the exchange runs ceil(n_h / g_block) blocks
+                            per Laplace point; set by the workspace budget) */
 } ltmp2_info;
 
 /*
  * Prepare a cell (Implementation section, step (i)): validates all inputs on
- * the host before any device call, uploads them, synthesises the orbitals on
- * the grid, computes and stores the overlap densities <a|e^{-iG.r}|j>
- * (Eq. SCHovrlp) and fixes the Laplace quadrature.
- *   miller [n_pw][3] int32   basis Miller indices (closed under m -> -m)
+ * the host before any device call, brings the orbitals to real form (as
+ * ltmp2_real_orbitals), uploads them, synthesises the orbitals on the grid,
+ * computes and stores the overlap densities <a|e^{-iG.r}|j> (Eq. SCHovrlp)
+ * and fixes the Laplace quadrature.
+ *   miller [n_pw][3] int32   basis Miller indices: closed under m -> -m,
+ *                            without duplicates, and every (m_y, m_z)
+ *                            column a run of consecutive m_x (a sphere);
+ *                            LTMP2_EINVAL otherwise
  *   eps    [n_states]        orbital energies, ascending
  *   coeff  [n_states][n_pw][2]  state-major coefficients c_p(G), (re, im)
  *   tau, w [n_tau]           quadrature (only with LTMP2_QUAD_GIVEN, else NULL)
@@ -134,14 +144,18 @@ ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller, const dou
  *   G_vir(r, r') = sum_a psi_a(r) exp(-(e_a - mu) tau) psi_a(r')
  * with mu = (e_HOMO + e_LUMO) / 2, written as doubles [nrows][n_r] to the
  * caller's device buffers (either may be NULL); r runs over the internal
- * transform grid (ltmp2_info.n_grid).  Diagnostic entry point.
+ * transform grid (ltmp2_info.n_grid).  The rows are computed in the
+ * context's precision by the same operand forms the energy uses (FP64, FP32,
+ * or split-BF16x3 operands with FP32 accumulation).  Diagnostic entry point.
  */
 ltmp2_status ltmp2_green(ltmp2_ctx* ctx, int itau, int row0, int nrows, void* gocc_dev,
                          void* gvir_dev);
 
 /*
- * Direct term at tau_itau: chi(r, r') = G_occ(r, r') G_vir(r', r) tile by
- * tile, its double Fourier transform
+ * Direct term at tau_itau (Eq. dLTMP2Compact at q = 0, the Laplace-transformed
+ * direct energy written with the Green's functions of the same equation):
+ * chi(r, r') = G_occ(r, r') G_vir(r', r) tile by tile, its double Fourier
+ * transform
  *   chi(G, G') = dV^2 sum_{r, r'} e^{-iG.r} chi(r, r') e^{iG'.r'}
  * on the auxiliary set and the Coulomb trace
  *   *e_direct_tau = -2 sum_{G, G'} v(G) v(G') |chi(G, G')|^2   (unweighted).
@@ -163,10 +177,12 @@ ltmp2_status ltmp2_exchange(ltmp2_ctx* ctx, int itau, int g_first, int g_count,
                             double* e_exchange_tau);
 
 /*
- * Full energy: E_d = sum_n w_n E_d(tau_n), E_x = sum_n w_n E_x(tau_n)
- * (Ha per cell).  per_tau (may be NULL) receives [2 n_tau] unweighted values
- * (E_d(tau_n), E_x(tau_n)) pairs; quad_err (may be NULL) the certified max
- * relative error of the quadrature.
+ * Full energy: the Laplace transform of the energy denominator (Eq. SCHLT)
+ * evaluated by the quadrature, E_d = sum_n w_n E_d(tau_n) and
+ * E_x = sum_n w_n E_x(tau_n) (Eqs. dLTMP2Compact and xLTMP2Compact at q = 0),
+ * summed in FP64 (Ha per cell).  per_tau (may be NULL) receives [2 n_tau]
+ * unweighted values (E_d(tau_n), E_x(tau_n)) pairs; quad_err (may be NULL)
+ * the certified max relative error of the quadrature.
  */
 ltmp2_status ltmp2_energy(ltmp2_ctx* ctx, double* e_direct, double* e_exchange,
                           double* per_tau, double* quad_err);
@@ -308,6 +324,22 @@ ltmp2_status ltmp2_batch_group(const ltmp2_batch* b, int g, int* n_fft, int* n_c
 ltmp2_status ltmp2_batch_cell(const ltmp2_batch* b, int k, ltmp2_info* info);
 void ltmp2_batch_destroy(ltmp2_batch* b);
 const char* ltmp2_batch_last_error(const ltmp2_batch* b);
+
+/*
+ * Host-only: orbitals that are real on the grid up to a phase per orbital
+ * (a non-degenerate Gamma-point eigenstate of a real potential, the paper's
+ * time-reversal subsection) are multiplied by the phase that makes them real;
+ * a block of degenerate orbitals (energies equal to 1e-9 relative) that is
+ * not real orbital by orbital is replaced by a real orthonormal basis of its
+ * span.  Energies of the method are unchanged by either step.
+ *   miller [n_pw][3], eps [n_states] ascending, coeff_in / coeff_out
+ *   [n_states][n_pw][2] (may alias); n_occ marks the occupied states.
+ * Returns LTMP2_EINVAL for a state with no real form (not time-reversal
+ * invariant), LTMP2_EGAP for a degenerate block across n_occ.  Touches no
+ * device.
+ */
+ltmp2_status ltmp2_real_orbitals(int n_pw, const int32_t* miller, int n_states, const double* eps,
+                                 int n_occ, const double* coeff_in, double* coeff_out);
 
 /* Release a context and all of its device memory (NULL is ignored). */
 void ltmp2_destroy(ltmp2_ctx* ctx);

@@ -49,6 +49,13 @@ int round_kmax(const Round& r) {
   return k;
 }
 
+int sched_kmax(const std::vector<std::vector<Round>>& sched) {
+  int k = 0;
+  for (const auto& rounds : sched)
+    for (const Round& r : rounds) k = std::max(k, round_kmax(r));
+  return k;
+}
+
 struct Group {
   int n = 0;
   std::vector<int> cells;
@@ -63,7 +70,9 @@ struct Group {
 thread_local std::string g_batch_error;
 
 std::mutex g_tune_mu;
-std::map<std::pair<int, int>, std::pair<int, int>> g_tune_cache;  // (n, prec) -> (sx, wg/CU)
+// (n, prec, largest kept set of the group) -> (sx, wg/CU): the slab tile that
+// fits shared memory depends on the kept set, so it is part of the key
+std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune_cache;
 
 }  // namespace
 
@@ -198,7 +207,8 @@ ltmp2_status run_all(ltmp2_batch* b) {
 
 // Time the fused pair launch of (tau 0, round 0) for each candidate tile.
 ltmp2_status tune_group(ltmp2_batch* b, Group& g) {
-  const std::pair<int, int> key{g.n, b->prec};
+  const int kmax_g = sched_kmax(g.sched);
+  const std::tuple<int, int, int> key{g.n, b->prec, kmax_g};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -216,8 +226,9 @@ ltmp2_status tune_group(ltmp2_batch* b, Group& g) {
     const int gb = std::min(c->gblock, c->nh);
     if ((s = exchange_block_prepare(c, 0, 0, gb))) return bfail(b, s, "tuning prepare: " + c->err);
   }
-  const int smax = b->prec == LTMP2_FP64 ? grid_ops<double>(g.n)->pair_sx_max(round_kmax(r0))
-                                         : grid_ops<float>(g.n)->pair_sx_max(round_kmax(r0));
+  // every round of the group must fit the chosen tile
+  const int smax = b->prec == LTMP2_FP64 ? grid_ops<double>(g.n)->pair_sx_max(kmax_g)
+                                         : grid_ops<float>(g.n)->pair_sx_max(kmax_g);
   std::vector<int> sxs{smax};
   if (smax > 1) sxs.push_back(slab_tile_at_most(g.n, smax - 1));
   hipEvent_t e0, e1;
@@ -263,10 +274,14 @@ extern "C" ltmp2_status ltmp2_batch_create(int n_cells, const ltmp2_params* para
   if (n_cells < 1 || !params || !miller || !eps || !coeff)
     return bfail(nullptr, LTMP2_EINVAL, "bad batch arguments");
   const int prec = params[0].prec;
+  // coefficients of each cell in real form (the caller's array when already real)
+  std::vector<std::vector<double>> creal(n_cells);
+  std::vector<const double*> cuse(n_cells);
   for (int k = 0; k < n_cells; ++k) {
     if (params[k].prec != prec) return bfail(nullptr, LTMP2_EINVAL, "cells differ in precision");
     ltmp2_status s = validate_inputs(&params[k], miller[k], eps[k], coeff[k],
-                                     tau ? tau[k] : nullptr, w ? w[k] : nullptr);
+                                     tau ? tau[k] : nullptr, w ? w[k] : nullptr, creal[k],
+                                     &cuse[k]);
     if (s) return bfail(nullptr, s, "cell " + std::to_string(k) + ": " + setup_error());
   }
   ltmp2_batch* b = new ltmp2_batch();
@@ -293,8 +308,9 @@ extern "C" ltmp2_status ltmp2_batch_create(int n_cells, const ltmp2_params* para
     c->own_scratch = false;
     if (mlp_weights) c->mlp_path = mlp_weights;
     b->cells.push_back(c);
-    ltmp2_status s = setup_cell(c, miller[k], eps[k], coeff[k], tau ? tau[k] : nullptr,
+    ltmp2_status s = setup_cell(c, miller[k], eps[k], cuse[k], tau ? tau[k] : nullptr,
                                 w ? w[k] : nullptr);
+    std::vector<double>().swap(creal[k]);
     if (s) {
       const std::string m = "cell " + std::to_string(k) + ": " + setup_error();
       ltmp2_batch_destroy(b);
@@ -397,7 +413,7 @@ extern "C" ltmp2_status ltmp2_batch_create(int n_cells, const ltmp2_params* para
         }
       }
     // largest slab tile allowed by shared memory for this group
-    const int km = round_kmax(g.sched[0][0]);
+    const int km = sched_kmax(g.sched);
     g.sx = b->prec == LTMP2_FP64 ? grid_ops<double>(g.n)->pair_sx_max(km)
                                  : grid_ops<float>(g.n)->pair_sx_max(km);
   }

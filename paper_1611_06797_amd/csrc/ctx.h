@@ -85,7 +85,16 @@ ltmp2_status exchange_block_prepare(ltmp2_ctx* c, int itau, int g0, int gb);
 ltmp2_status exchange_reduce(ltmp2_ctx* c, int itau, int g_first, int g_count);
 ltmp2_status setup_cell(ltmp2_ctx* c, const int32_t* miller, const double* eps,
                         const double* coeff, const double* tau, const double* w);
+// Validation of a cell's inputs; *use receives the coefficients to pass on
+// (the caller's, or their real form held in `store`).
 ltmp2_status validate_inputs(const ltmp2_params* p, const int32_t* miller, const double* eps,
-                             const double* coeff, const double* tau, const double* w);
+                             const double* coeff, const double* tau, const double* w,
+                             std::vector<double>& store, const double** use);
 const std::string& setup_error();
+void set_setup_error(const std::string& msg);
+// Orbitals real up to a phase (or degenerate blocks with a real basis) to
+// real form (real_orbitals.cpp); `out` stays empty if nothing changes.
+ltmp2_status real_orbitals(int npw, const int32_t* miller, int nst, const double* eps, int nocc,
+                           const double* coeff, std::vector<double>& out, bool* changed,
+                           std::string& err);
 }  // namespace ltmp2

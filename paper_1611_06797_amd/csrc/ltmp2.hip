@@ -143,30 +143,53 @@ ltmp2_status validate(const ltmp2_params* p, const int32_t* miller, const double
   for (int k = 0; k < npw; ++k)
     if (!pos.count(std::make_tuple(-miller[3 * k], -miller[3 * k + 1], -miller[3 * k + 2])))
       return fail(nullptr, LTMP2_EINVAL, "basis not closed under G -> -G");
+  // the transforms walk each (ky, kz) column of the sphere as a run of
+  // consecutive kx: a basis with a hole inside a column is rejected
+  {
+    std::map<std::pair<int, int>, std::vector<int>> cols;
+    for (int k = 0; k < npw; ++k)
+      cols[{miller[3 * k + 1], miller[3 * k + 2]}].push_back(miller[3 * k]);
+    for (auto& kv : cols) {
+      std::vector<int>& xs = kv.second;
+      std::sort(xs.begin(), xs.end());
+      if (xs.back() - xs.front() + 1 != int(xs.size()))
+        return fail(nullptr, LTMP2_EINVAL,
+                    "basis column (ky, kz) = (" + std::to_string(kv.first.first) + ", " +
+                        std::to_string(kv.first.second) + ") is not a run of consecutive kx");
+    }
+  }
   for (int k = 0; k < nst; ++k) {
     if (!std::isfinite(eps[k])) return fail(nullptr, LTMP2_EINVAL, "non-finite orbital energy");
     if (k > 0 && eps[k] < eps[k - 1]) return fail(nullptr, LTMP2_EINVAL, "eps must be ascending");
   }
   if (!(eps[p->n_occ] - eps[p->n_occ - 1] > 1e-8))
     return fail(nullptr, LTMP2_EGAP, "HOMO-LUMO gap <= 1e-8 Ha");
-  std::vector<int> negi(npw);
-  for (int k = 0; k < npw; ++k)
-    negi[k] = pos[std::make_tuple(-miller[3 * k], -miller[3 * k + 1], -miller[3 * k + 2])];
   for (int s = 0; s < nst; ++s) {
     const double* c = coeff + 2 * size_t(s) * npw;
-    double nrm = 0.0, asym = 0.0;
+    double nrm = 0.0;
     for (int k = 0; k < npw; ++k) {
       if (!std::isfinite(c[2 * k]) || !std::isfinite(c[2 * k + 1]))
         return fail(nullptr, LTMP2_EINVAL, "non-finite coefficient");
       nrm += c[2 * k] * c[2 * k] + c[2 * k + 1] * c[2 * k + 1];
-      const int m = negi[k];
-      asym = std::max(asym, std::fabs(c[2 * m] - c[2 * k]) + std::fabs(c[2 * m + 1] + c[2 * k + 1]));
     }
     if (std::fabs(nrm - 1.0) > 1e-8) return fail(nullptr, LTMP2_EINVAL, "state not normalised");
-    if (asym > 1e-10)
-      return fail(nullptr, LTMP2_EINVAL,
-                  "orbital " + std::to_string(s) + " is not real on the grid (c(-G) != conj c(G))");
   }
+  return LTMP2_OK;
+}
+
+// Validation, then the orbitals brought to real form (real_orbitals.cpp):
+// *use points at the caller's coefficients or at `store`.
+ltmp2_status validate_and_realise(const ltmp2_params* p, const int32_t* miller, const double* eps,
+                                  const double* coeff, const double* tau, const double* w,
+                                  std::vector<double>& store, const double** use) {
+  ltmp2_status s = validate(p, miller, eps, coeff, tau, w);
+  if (s) return s;
+  const int nst = p->n_states ? p->n_states : p->n_pw;
+  bool changed = false;
+  std::string err;
+  s = real_orbitals(p->n_pw, miller, nst, eps, p->n_occ, coeff, store, &changed, err);
+  if (s) return fail(nullptr, s, err);
+  *use = changed ? store.data() : coeff;
   return LTMP2_OK;
 }
 
@@ -732,6 +755,42 @@ ltmp2_status green_t(ltmp2_ctx* c, int itau, int row0, int nrows, double* gocc, 
   return LTMP2_OK;
 }
 
+// Split-BF16x3 contexts: the rows come from the same split operands and
+// matrix-core kernel family as the chi tiles (sqrt-scaled orbitals split into
+// hi / lo BF16, hi*hi + hi*lo + lo*hi in FP32), computed on whole 128-row
+// tiles into the chi scratch and widened to double.
+ltmp2_status green_split3(ltmp2_ctx* c, int itau, int row0, int nrows, double* gocc,
+                          double* gvir) {
+  const double* fo = c->d_fo + size_t(itau) * c->no;
+  const double* fv = c->d_fv + size_t(itau) * c->nv;
+  const float* psi = static_cast<const float*>(c->d_psi);
+  ltmp2_status s = launch_split3(psi, c->nrp, c->no, c->kpo, int(c->nrp), c->nrp, fo, 2,
+                                 c->d_psi3h, c->d_psi3l, 0, c->stream);
+  if (!s)
+    s = launch_split3(psi + long(c->no) * c->nrp, c->nrp, c->nv, c->kpv, int(c->nrp), c->nrp, fv,
+                      2, c->d_psi3h, c->d_psi3l, c->kpo / 8, c->stream);
+  if (s) return fail(c, s, "operand split launch failed");
+  // whole 128-row tiles, so every operand row read stays inside the n_rp
+  // padded rows of the split arrays
+  const long r0 = long(row0) / 128 * 128;
+  const int M = int(std::min<long>(c->nrp, (long(row0) + nrows + 127) / 128 * 128) - r0);
+  for (int which = 0; which < 2; ++which) {
+    double* out = which ? gvir : gocc;
+    if (!out) continue;
+    const long off = which ? long(c->kpo / 8) * c->nrp * 8 : 0;
+    const __bf16* hi = static_cast<const __bf16*>(c->d_psi3h) + off;
+    const __bf16* lo = static_cast<const __bf16*>(c->d_psi3l) + off;
+    s = launch_mm3(hi, lo, c->nrp, r0, hi, lo, c->nrp, static_cast<float*>(c->d_chi),
+                   (long)c->nr, M, c->nr, which ? c->kpv : c->kpo, nullptr, 1, 1, c->stream);
+    if (s) return fail(c, s, "Green's-function split GEMM launch failed");
+    const long cnt = long(nrows) * c->nr;
+    hipLaunchKernelGGL(k_widen, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, c->stream,
+                       static_cast<const float*>(c->d_chi) + (row0 - r0) * long(c->nr), out, cnt);
+    if ((s = check_launch(c, "k_widen"))) return s;
+  }
+  return LTMP2_OK;
+}
+
 }  // namespace
 
 namespace ltmp2 {
@@ -752,10 +811,12 @@ ltmp2_status setup_cell(ltmp2_ctx* c, const int32_t* miller, const double* eps,
   return setup_impl(c, miller, eps, coeff, tau, w);
 }
 ltmp2_status validate_inputs(const ltmp2_params* p, const int32_t* miller, const double* eps,
-                             const double* coeff, const double* tau, const double* w) {
-  return validate(p, miller, eps, coeff, tau, w);
+                             const double* coeff, const double* tau, const double* w,
+                             std::vector<double>& store, const double** use) {
+  return validate_and_realise(p, miller, eps, coeff, tau, w, store, use);
 }
 const std::string& setup_error() { return g_setup_error; }
+void set_setup_error(const std::string& msg) { g_setup_error = msg; }
 }  // namespace ltmp2
 
 extern "C" ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller,
@@ -764,7 +825,8 @@ extern "C" ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller
                                     ltmp2_ctx** out) {
   if (!out) return fail(nullptr, LTMP2_EINVAL, "out is NULL");
   *out = nullptr;
-  ltmp2_status s = validate(p, miller, eps, coeff, tau, w);
+  std::vector<double> creal;
+  ltmp2_status s = validate_and_realise(p, miller, eps, coeff, tau, w, creal, &coeff);
   if (s) return s;
   ltmp2_ctx* c = new ltmp2_ctx();
   c->prm = *p;
@@ -787,11 +849,15 @@ extern "C" ltmp2_status ltmp2_green(ltmp2_ctx* c, int itau, int row0, int nrows,
   if (row0 < 0 || nrows < 0 || row0 + nrows > c->nr)
     return fail(c, LTMP2_EINVAL, "row range outside [0, n_r)");
   if (nrows == 0) return LTMP2_OK;
-  s = (c->prm.prec == LTMP2_FP64)
-          ? green_t<double, kF64>(c, itau, row0, nrows, static_cast<double*>(gocc),
-                                  static_cast<double*>(gvir))
-          : green_t<float, kF32>(c, itau, row0, nrows, static_cast<double*>(gocc),
-                                 static_cast<double*>(gvir));
+  if (c->prm.prec == LTMP2_FP64)
+    s = green_t<double, kF64>(c, itau, row0, nrows, static_cast<double*>(gocc),
+                              static_cast<double*>(gvir));
+  else if (c->prm.prec == LTMP2_FP32)
+    s = green_t<float, kF32>(c, itau, row0, nrows, static_cast<double*>(gocc),
+                             static_cast<double*>(gvir));
+  else
+    s = green_split3(c, itau, row0, nrows, static_cast<double*>(gocc),
+                     static_cast<double*>(gvir));
   if (s) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LTMP2_OK;
@@ -877,6 +943,7 @@ extern "C" ltmp2_status ltmp2_get_info(const ltmp2_ctx* c, ltmp2_info* info) {
   info->device_bytes = c->bytes;
   info->quad_flags = c->quad_flags;
   info->n_grid = c->n;
+  info->g_block = c->gblock;
   return LTMP2_OK;
 }
 

@@ -28,7 +28,7 @@ EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_
             "ltmp2_mlp_last_error", "ltmp2_remez_polish", "ltmp2_batch_create",
             "ltmp2_batch_energy", "ltmp2_batch_info", "ltmp2_batch_group", "ltmp2_batch_cell",
             "ltmp2_batch_destroy", "ltmp2_batch_last_error", "ltmp2_batch_set_timing",
-            "ltmp2_batch_get_timing")
+            "ltmp2_batch_get_timing", "ltmp2_real_orbitals")
 MLP_NPARAM = 5976
 STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
 
@@ -45,7 +45,8 @@ class Info(C.Structure):
     _fields_ = [("n_r", C.c_int), ("n_g", C.c_int), ("n_h", C.c_int), ("n_pw", C.c_int),
                 ("n_occ", C.c_int), ("n_vir", C.c_int), ("n_tau", C.c_int),
                 ("x_min", C.c_double), ("x_max", C.c_double), ("quad_delta", C.c_double),
-                ("device_bytes", C.c_size_t), ("quad_flags", C.c_int), ("n_grid", C.c_int)]
+                ("device_bytes", C.c_size_t), ("quad_flags", C.c_int), ("n_grid", C.c_int),
+                ("g_block", C.c_int)]
 
 
 class BatchStats(C.Structure):
@@ -121,6 +122,7 @@ def load(path: str = LIB_PATH):
     lib.ltmp2_batch_destroy.restype = None
     lib.ltmp2_batch_last_error.argtypes = [vp]
     lib.ltmp2_batch_last_error.restype = C.c_char_p
+    lib.ltmp2_real_orbitals.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, vp, vp]
     lib.ltmp2_mlp_last_error.argtypes = []
     lib.ltmp2_mlp_last_error.restype = C.c_char_p
     for name in ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
@@ -130,7 +132,7 @@ def load(path: str = LIB_PATH):
                  "ltmp2_mlp_grad", "ltmp2_mlp_train", "ltmp2_learned_quadrature",
                  "ltmp2_batch_create", "ltmp2_batch_energy", "ltmp2_batch_info",
                  "ltmp2_batch_group", "ltmp2_batch_cell", "ltmp2_batch_set_timing",
-                 "ltmp2_batch_get_timing"):
+                 "ltmp2_batch_get_timing", "ltmp2_real_orbitals"):
         getattr(lib, name).restype = C.c_int
     lib.ltmp2_supported_grids.restype = C.c_int
     _lib = lib
@@ -161,6 +163,16 @@ def quadrature(x_min: float, x_max: float, n_tau: int):
     d = C.c_double()
     _check(lib, lib.ltmp2_quadrature(x_min, x_max, n_tau, _ptr(tau), _ptr(w), C.byref(d)))
     return tau, w, d.value
+
+
+def real_orbitals(miller, eps, coeff, n_occ):
+    """Host-only: coefficients brought to real form on the grid (complex128 [n_states, n_pw])."""
+    lib = load()
+    m, e, c = _cell_arrays(miller, eps, coeff)
+    out = np.zeros_like(c)
+    _check(lib, lib.ltmp2_real_orbitals(m.shape[0], _ptr(m), e.shape[0], _ptr(e), int(n_occ),
+                                        _ptr(c), _ptr(out)))
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def _mcheck(lib, st):

@@ -142,6 +142,35 @@ def _real_basis(miller: np.ndarray) -> np.ndarray:
     return U
 
 
+def _real_basis_sparse(miller: np.ndarray):
+    """The unitary of _real_basis as a sparse matrix (two entries per column)."""
+    import scipy.sparse as sp
+    U = _real_basis(miller) if miller.shape[0] <= 64 else None
+    if U is not None:
+        return sp.csc_matrix(U)
+    npw = miller.shape[0]
+    index = {tuple(v): k for k, v in enumerate(miller.tolist())}
+    rows, cols, vals = [], [], []
+    col = 0
+    s = 1.0 / math.sqrt(2.0)
+    for k, v in enumerate(miller.tolist()):
+        t = tuple(v)
+        if t == (0, 0, 0):
+            rows.append(k); cols.append(col); vals.append(1.0)
+            col += 1
+            continue
+        first = next(c for c in t if c != 0)
+        if first < 0:
+            continue
+        kp = index[(-t[0], -t[1], -t[2])]
+        rows += [k, kp, k, kp]
+        cols += [col, col, col + 1, col + 1]
+        vals += [s, s, 1j * s, -1j * s]
+        col += 2
+    assert col == npw
+    return sp.csc_matrix((np.array(vals, complex), (rows, cols)), shape=(npw, npw))
+
+
 def potential_box(miller: np.ndarray, L: float, seed: int, amp: float):
     """Seeded Hermitised potential V on the box of difference vectors.
 
@@ -185,8 +214,8 @@ def make_cell(spec: CellSpec):
     """
     miller = orbital_miller(spec.L, spec.n, spec.ecut)
     H = hamiltonian(miller, spec.L, spec.seed, spec.amp)
-    U = _real_basis(miller)
-    Hr = U.conj().T @ H @ U
+    U = _real_basis_sparse(miller)
+    Hr = np.asarray((U.conj().T @ (U.T @ H.T).T))
     if np.abs(Hr.imag).max() > 1e-10 * max(1.0, np.abs(Hr.real).max()):
         raise RuntimeError("Hamiltonian is not time-reversal invariant")
     Hr = 0.5 * (Hr.real + Hr.real.T)
@@ -196,6 +225,24 @@ def make_cell(spec: CellSpec):
     sgn = np.sign(R[piv, np.arange(R.shape[1])])
     R = R * sgn[None, :]
     coeff = (U @ R).T.copy()
+    return miller, eps.copy(), coeff
+
+
+def make_cell_complex(spec: CellSpec, phase_seed: int | None = None):
+    """(miller, eps, coeff) from a plain complex Hermitian eigensolver.
+
+    H is diagonalised as given (no real basis), so each state carries
+    whatever phase the eigensolver returns; with phase_seed, every state is
+    further multiplied by a seeded random phase e^{i theta_p}.  The orbitals
+    are real on the grid only up to these phases.
+    """
+    miller = orbital_miller(spec.L, spec.n, spec.ecut)
+    H = hamiltonian(miller, spec.L, spec.seed, spec.amp)
+    eps, V = np.linalg.eigh(H)
+    coeff = V.T.copy()
+    if phase_seed is not None:
+        th = np.random.default_rng(phase_seed).uniform(0.0, 2.0 * math.pi, size=coeff.shape[0])
+        coeff *= np.exp(1j * th)[:, None]
     return miller, eps.copy(), coeff
 
 

@@ -89,9 +89,17 @@ def test_validation_paths(lib, cell):
     e2 = e.copy()
     e2[s.n_occ] = e2[s.n_occ - 1]
     _expect(lib, G, lambda: _setup(lib, s, m, e2, c))                # zero gap
-    c2 = c * np.exp(0.3j)
-    msg = _expect(lib, E, lambda: _setup(lib, s, m, e, c2))          # not real on the grid
+    c2 = c.copy()                                                     # one state a single
+    k = int(np.argmax(m[:, 0]))                                       # plane wave G != 0:
+    c2[s.n_occ + 2] = 0.0                                             # no real form
+    c2[s.n_occ + 2, k] = 1.0
+    msg = _expect(lib, E, lambda: _setup(lib, s, m, e, c2))
     assert "real" in msg
+    holed = np.ones(len(m), bool)                                     # symmetric hole inside
+    mid = [k for k, v in enumerate(m.tolist()) if v[1] == 0 and v[2] == 0 and abs(v[0]) == 1]
+    holed[mid] = False                                                # the (0, 0) column
+    msg = _expect(lib, E, lambda: _setup(lib, s, m[holed], e[holed], c[np.ix_(holed, holed)]))
+    assert "consecutive" in msg
     c3 = c * 1.01
     _expect(lib, E, lambda: _setup(lib, s, m, e, c3))                # not normalised
     c4 = c.copy()
@@ -155,3 +163,90 @@ def test_mlp_init_and_weight_file(lib, tmp_path):
     f = tmp_path / "w.bin"
     lib.write_mlp_weights(str(f), p)
     assert np.array_equal(lib.read_mlp_weights(str(f)), p)
+
+
+def _is_real_on_grid(m, c, tol=1e-12):
+    pos = {tuple(v): k for k, v in enumerate(m.tolist())}
+    neg = np.array([pos[(-a, -b, -d)] for a, b, d in m.tolist()])
+    return np.abs(c[:, neg] - np.conj(c)).max() <= tol
+
+
+def test_real_orbitals_removes_phases(lib, cell):
+    # states real up to a phase each: the helper returns them real, equal to
+    # the real states up to a sign
+    s, (m, e, c) = cell
+    th = np.random.default_rng(3).uniform(0, 2 * np.pi, len(e))
+    out = lib.real_orbitals(m, e, c * np.exp(1j * th)[:, None], s.n_occ)
+    assert _is_real_on_grid(m, out)
+    ov = np.einsum("pg,pg->p", np.conj(c), out)
+    assert np.allclose(np.abs(ov), 1.0, atol=1e-12) and np.allclose(ov.imag, 0.0, atol=1e-12)
+    assert np.array_equal(lib.real_orbitals(m, e, c, s.n_occ), c)   # real input untouched
+
+
+def test_real_orbitals_complex_eigensolver(lib):
+    # a complex Hermitian eigensolver's output (arbitrary phases) on the
+    # 12^3 workload: real on the grid afterwards, same states up to a sign
+    from synthetic import make_cell_complex
+    m, e, c = make_cell_complex(C1, phase_seed=5)
+    mr, er, cr = make_cell(C1)
+    assert np.array_equal(m, mr) and np.allclose(e, er, atol=1e-10)
+    out = lib.real_orbitals(m, e, c, C1.n_occ)
+    assert _is_real_on_grid(m, out)
+    ov = np.abs(np.einsum("pg,pg->p", np.conj(cr), out))
+    assert np.allclose(ov, 1.0, atol=1e-8)
+
+
+def test_real_orbitals_degenerate_block(lib, cell):
+    # two degenerate virtual states mixed by a complex rotation: neither is
+    # real up to a phase, the pair is time-reversal invariant; the helper
+    # returns a real orthonormal basis of the same span
+    s, (m, e, c) = cell
+    a, b = s.n_occ + 4, s.n_occ + 5
+    e2 = e.copy()
+    e2[b] = e2[a]
+    c2 = c.copy()
+    c2[a] = (c[a] + 1j * c[b]) / np.sqrt(2.0)
+    c2[b] = (c[a] - 1j * c[b]) / np.sqrt(2.0)
+    out = lib.real_orbitals(m, e2, c2, s.n_occ)
+    assert _is_real_on_grid(m, out, 1e-10)
+    blk = out[[a, b]]
+    assert np.allclose(blk @ np.conj(blk).T, np.eye(2), atol=1e-12)
+    P0 = c[[a, b]].T @ np.conj(c[[a, b]])
+    P1 = blk.T @ np.conj(blk)
+    assert np.abs(P0 - P1).max() <= 1e-12
+    others = np.setdiff1d(np.arange(len(e)), [a, b])
+    assert np.array_equal(out[others], c[others])
+    # without the degeneracy the same input has no real form
+    with pytest.raises(lib.LTMP2Error) as ex:
+        lib.real_orbitals(m, e, c2, s.n_occ)
+    assert ex.value.status == 1
+
+
+def test_real_orbitals_block_across_the_gap(lib, cell):
+    s, (m, e, c) = cell
+    a, b = s.n_occ - 1, s.n_occ
+    e2 = e.copy()
+    e2[b] = e2[a]
+    c2 = c.copy()
+    c2[a] = (c[a] + 1j * c[b]) / np.sqrt(2.0)
+    c2[b] = (c[a] - 1j * c[b]) / np.sqrt(2.0)
+    with pytest.raises(lib.LTMP2Error) as ex:
+        lib.real_orbitals(m, e2, c2, s.n_occ)
+    assert ex.value.status == 2
+
+
+@pytest.mark.parametrize("xmin,xmax,n", [(0.122, 16.2, 8), (0.037, 46.4, 8), (0.5, 30.0, 6),
+                                         (0.0045, 65.3, 10), (0.05, 500.0, 12)])
+def test_host_quadrature_equioscillates(lib, xmin, xmax, n):
+    # the library's fit is certified on its own: the relative error on the
+    # unit interval [1, max(R, R_floor)] has 2 n + 1 alternating extrema of
+    # equal size (alternation theorem), located by the oracle's extremum
+    # search, and that size is the delta the library reports
+    from oracle.quadrature import alternation_points, r_floor
+    t, w, d = lib.quadrature(xmin, xmax, n)
+    R = max(xmax / xmin, r_floor(n))
+    ys, es, emax = alternation_points(n, R, np.log(t * xmin), np.log(w * xmin))
+    assert len(ys) == 2 * n + 1
+    assert np.all(np.sign(es[1:]) == -np.sign(es[:-1]))
+    assert (np.abs(es).max() - np.abs(es).min()) <= 1e-6 * np.abs(es).min()
+    assert abs(d - np.abs(es).max()) <= 1e-6 * d

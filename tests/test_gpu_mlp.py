@@ -103,3 +103,22 @@ def test_learned_mode_in_setup_and_fallback(L, tmp_path):
         assert ctx.info.quad_flags == 6
         t2, w2, d2 = ctx.get_quadrature()
     assert np.allclose(t2, to, rtol=1e-9)
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+@pytest.mark.parametrize("x_min,x_max,n", [(0.0045, 65.3, 10), (0.0023, 65.3, 10)])
+def test_learned_quadrature_at_the_40_cube_range(L, x_min, x_max, n):
+    # the 40^3 cell's denominator range lies outside the training ranges
+    # (x_min below 0.05 Ha, R = 1.45e4 and 2.8e4 above 1e4): the proposal is
+    # either certified after 3 Remez passes or replaced by the plain fit, and
+    # in both cases the error is the oracle's minimax error
+    from oracle.quadrature import minimax_laplace
+    p = L.read_mlp_weights(WEIGHTS)
+    _say("learned quadrature out of range", x_min, x_max, n)
+    tau, w, d, fl = L.learned_quadrature(p, x_min, x_max, n)
+    to, wo, do = minimax_laplace(x_min, x_max, n)
+    print(f"[mlp ood] R={x_max / x_min:.3g} flags={fl} delta={d:.6e} oracle={do:.6e}", flush=True)
+    assert fl & 3
+    assert abs(d - do) <= 2e-6 * do
+    if fl & 1:
+        assert np.allclose(tau, to, rtol=1e-4) and np.allclose(w, wo, rtol=1e-4)

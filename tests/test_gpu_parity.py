@@ -262,3 +262,106 @@ def test_c3_occupied_subset_vs_oracle(torch_cuda):
             assert abs(dd) <= 1e-9 * abs(ref["e_d_lt"]) and abs(dx) <= 1e-9 * abs(ref["e_x_lt"])
             assert np.allclose(pt[:, 0], ref["per_tau_d"], rtol=1e-9, atol=0)
             assert np.allclose(pt[:, 1], ref["per_tau_x"], rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_c1_phased_inputs(torch_cuda, prec):
+    # orbitals from a plain complex eigensolver with seeded random phases:
+    # real on the grid only up to a phase each.  The library brings them to
+    # real form at setup; the energy is phase invariant, and the oracle works
+    # with the phased orbitals as given.
+    from synthetic import make_cell_complex
+    m, e, c = make_cell_complex(C1, phase_seed=7)
+    _say("C1 phased inputs, prec", prec)
+    P = _oracle(C1, m, e, c)
+    from oracle.quadrature import minimax_laplace
+    tau, w, _ = minimax_laplace(*P.x_range(), C1.n_tau)
+    ref = P.energies(tau, w)
+    with _ctx(C1, m, e, c, tau=tau, w=w, prec=prec) as ctx:
+        ed, ex, pt, qe = ctx.energy()
+    dd, dx = ed - ref["e_d_lt"], ex - ref["e_x_lt"]
+    print(f"[phased prec={prec}] dE_d={dd:.3e} dE_x={dx:.3e}", flush=True)
+    assert abs(dd) < C1.n_occ * 1e-6 and abs(dx) < C1.n_occ * 1e-6
+    if prec == 0:
+        assert abs(dd) <= 1e-9 * abs(ref["e_d_lt"]) and abs(dx) <= 1e-9 * abs(ref["e_x_lt"])
+        assert np.allclose(pt[:, 0], ref["per_tau_d"], rtol=1e-9, atol=0)
+        assert np.allclose(pt[:, 1], ref["per_tau_x"], rtol=1e-9, atol=0)
+
+
+def test_c1_multi_block_exchange(torch_cuda):
+    # 12 occupied orbitals (two 8 x 8 blocks of occupied pairs, one ragged) and
+    # a workspace cap that cuts the outer G' loop into several
+    # transformed-state blocks; per-tau values against the oracle
+    spec = CellSpec(L=8.0, n=12, ecut=6.0, eaux=4.0, n_occ=12, n_tau=6, seed=0)
+    m, e, c = make_cell(spec)
+    P = _oracle(spec, m, e, c)
+    from oracle.quadrature import minimax_laplace
+    tau, w, _ = minimax_laplace(*P.x_range(), spec.n_tau)
+    ref = P.energies(tau, w)
+    with _ctx(spec, m, e, c, tau=tau, w=w) as ctx:
+        full_bytes, nh = ctx.info.device_bytes, ctx.info.n_h
+        assert ctx.info.g_block == nh
+    cap, blocks = full_bytes, 1
+    for frac in (0.9, 0.8, 0.7, 0.65, 0.6, 0.55):
+        cap = int(full_bytes * frac)
+        try:
+            with _ctx(spec, m, e, c, tau=tau, w=w, workspace_cap=cap) as ctx:
+                gb = ctx.info.g_block
+        except Exception:
+            break
+        if gb * 3 <= nh:
+            break
+    _say("C1 multi-block exchange: n_h", nh, "cap", cap)
+    with _ctx(spec, m, e, c, tau=tau, w=w, workspace_cap=cap) as ctx:
+        gb = ctx.info.g_block
+        ed, ex, pt, qe = ctx.energy()
+    print(f"[multi-block] n_h={nh} g_block={gb} dE_d={ed - ref['e_d_lt']:.3e} "
+          f"dE_x={ex - ref['e_x_lt']:.3e}", flush=True)
+    assert gb * 2 <= nh
+    assert np.allclose(pt[:, 0], ref["per_tau_d"], rtol=1e-9, atol=0)
+    assert np.allclose(pt[:, 1], ref["per_tau_x"], rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 1e-4)])
+def test_c1_chi_GG_mixed(c1_case, torch_cuda, prec, tol):
+    # chi(G, G') element by element in the FP32 and split-BF16x3 forms against
+    # the FP64 oracle; bound relative to the largest element
+    torch = torch_cuda
+    m, e, c, P, tau, w, ref = c1_case
+    _say("C1 chi(G,G') prec", prec)
+    with _ctx(C1, m, e, c, tau=tau, w=w, prec=prec) as ctx:
+        ng = ctx.info.n_g
+        out = torch.zeros((ng, ng), dtype=torch.complex128, device="cuda")
+        edt = ctx.chi(3, out)
+        aux = ctx.aux_miller()
+    pos = {tuple(v): k for k, v in enumerate(P.aux.tolist())}
+    idx = np.array([pos[tuple(v)] for v in aux.tolist()])
+    Cref = P.chi_GG(tau[3])[np.ix_(idx, idx)]
+    err = np.abs(out.cpu().numpy() - Cref).max() / np.abs(Cref).max()
+    print(f"[chi prec={prec}] max |dchi| / max |chi| = {err:.3e}; "
+          f"E_d(tau) rel {abs(edt / ref['per_tau_d'][3] - 1):.3e}", flush=True)
+    assert err <= tol
+
+
+def test_c1_green_rows_bf16x3(c1_case, torch_cuda):
+    # G_occ / G_vir rows of a split-BF16x3 context come from its split
+    # operands (hi*hi + hi*lo + lo*hi, FP32 accumulation): against the oracle
+    torch = torch_cuda
+    m, e, c, P, tau, w, ref = c1_case
+    n = C1.n
+    nr = n ** 3
+    perm = _lib_to_nat(n)
+    Go, Gv = P.green(tau[4])
+    _say("C1 green rows bf16x3")
+    with _ctx(C1, m, e, c, tau=tau, w=w, prec=2) as ctx:
+        for row0, nrows in [(0, 64), (300, 100), (nr - 5, 5)]:
+            go = torch.zeros((nrows, nr), dtype=torch.float64, device="cuda")
+            gv = torch.zeros((nrows, nr), dtype=torch.float64, device="cuda")
+            ctx.green(4, row0, nrows, go, gv)
+            rows = perm[row0:row0 + nrows]
+            ro = Go[rows][:, perm].real
+            rv = Gv[rows][:, perm].real
+            eo = np.abs(go.cpu().numpy() - ro).max() / np.abs(Go).max()
+            ev = np.abs(gv.cpu().numpy() - rv).max() / np.abs(Gv).max()
+            print(f"[green bf16x3 rows {row0}+{nrows}] occ {eo:.3e} vir {ev:.3e}", flush=True)
+            assert eo < 1e-4 and ev < 1e-4
