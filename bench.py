@@ -308,6 +308,23 @@ def cpu_baseline_batch(specs, data, infos):
                       + ", ".join(notes) + f"; batch total {total:.0f}s by pair operation count"}
 
 
+def cached_cell(spec, cache_dir):
+    """make_cell(spec), stored in / read back from cache_dir when given."""
+    import numpy as np
+    from synthetic import make_cell
+    if not cache_dir:
+        return make_cell(spec)
+    tag = f"cell_L{spec.L}_n{spec.n}_e{spec.ecut}_s{spec.seed}_a{spec.amp}"
+    path = os.path.join(cache_dir, tag + ".npz")
+    if os.path.exists(path):
+        with np.load(path) as z:
+            return z["miller"], z["eps"], z["coeff"]
+    m, e, c = make_cell(spec)
+    os.makedirs(cache_dir, exist_ok=True)
+    np.savez(path, miller=m, eps=e, coeff=c)
+    return m, e, c
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +341,8 @@ def main():
                     help="run one 1 GiB copy kernel first (scale for HBM counter runs)")
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 form beside the headline form")
+    ap.add_argument("--cell-cache", default=None,
+                    help="directory for the generated cell arrays (reused when present)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs the LTMP2 path on one GPU only (no sharded "
@@ -341,7 +360,7 @@ def main():
     spec = workload(args.config)
     log("workload", spec)
     t = time.time()
-    m, e, c = make_cell(spec)
+    m, e, c = cached_cell(spec, args.cell_cache)
     log(f"cell ready ({time.time() - t:.1f}s): n_pw={m.shape[0]}")
     torch.cuda.set_device(0)
     if args.copy_probe:
