@@ -365,3 +365,45 @@ def test_c1_green_rows_bf16x3(c1_case, torch_cuda):
             ev = np.abs(gv.cpu().numpy() - rv).max() / np.abs(Gv).max()
             print(f"[green bf16x3 rows {row0}+{nrows}] occ {eo:.3e} vir {ev:.3e}", flush=True)
             assert eo < 1e-4 and ev < 1e-4
+
+
+def _subset16(name, spec):
+    """Oracle energy of a 16-orbital occupied subset (stored by
+    tests/golden/make_subsets.py) against every precision form: two 8 x 8
+    blocks of occupied pairs on the full transform grid, all virtuals."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"{name}_subset16.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet")
+    with open(path) as f:
+        ref = json.load(f)
+    m, e, c = make_cell(spec)
+    occ = np.array(ref["occ"])
+    tau, w = np.array(ref["tau"]), np.array(ref["w"])
+    sel = np.concatenate([occ, np.arange(spec.n_occ, len(e))])
+    sub = CellSpec(L=spec.L, n=spec.n, ecut=spec.ecut, eaux=spec.eaux, n_occ=len(occ),
+                   n_tau=spec.n_tau, seed=spec.seed)
+    for prec in (0, 1, 2):
+        _say(f"{name} 16-orbital subset, prec {prec}")
+        with _ctx(sub, m, e[sel], c[sel], tau=tau, w=w, prec=prec) as ctx:
+            ed, ex, pt, qe = ctx.energy()
+            gb, nh = ctx.info.g_block, ctx.info.n_h
+        dd, dx = ed - ref["e_d_lt"], ex - ref["e_x_lt"]
+        print(f"[{name}-subset16 prec={prec}] g_block={gb}/{nh} E_d={ed:.10f} dE_d={dd:.3e} "
+              f"E_x={ex:.10f} dE_x={dx:.3e}", flush=True)
+        assert abs(dd) < len(occ) * 1e-6 and abs(dx) < len(occ) * 1e-6
+        if prec == 0:
+            assert abs(dd) <= 1e-9 * abs(ref["e_d_lt"]) and abs(dx) <= 1e-9 * abs(ref["e_x_lt"])
+            assert np.allclose(pt[:, 0], ref["per_tau_d"], rtol=1e-9, atol=0)
+            assert np.allclose(pt[:, 1], ref["per_tau_x"], rtol=1e-9, atol=0)
+
+
+def test_c2_subset16_vs_oracle(torch_cuda):
+    from synthetic import C2
+    _subset16("c2", C2)
+
+
+def test_c3_subset16_vs_oracle(torch_cuda):
+    from synthetic import C3
+    _subset16("c3", C3)
