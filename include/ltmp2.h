@@ -257,6 +257,21 @@ ltmp2_status ltmp2_mlp_dataset(int count, uint64_t seed, double dmin_lo, double 
 ltmp2_status ltmp2_mlp_forward(const float* params, const float* X, int n, float* Y,
                                void* hip_stream);
 
+/*
+ * Network outputs for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops): the same forward pass as
+ * ltmp2_mlp_forward on caller-owned DEVICE arrays, params_dev
+ * [LTMP2_MLP_NPARAM], X_dev [n][3], Y_dev [n][24] (floats), enqueued on
+ * hip_stream without synchronising and without any allocation; the hidden
+ * activations use a fixed 8 MiB device array of the library (at most
+ * LTMP2_MLP_NOALLOC_MAX_ROWS rows per call, else LTMP2_EINVAL).  Each GPU
+ * holds one such array for the life of the process: calls that overlap on
+ * one GPU race.
+ */
+#define LTMP2_MLP_NOALLOC_MAX_ROWS 16384
+ltmp2_status ltmp2_mlp_forward_noalloc(const float* params_dev, const float* X_dev, int n,
+                                       float* Y_dev, void* hip_stream);
+
 /* Gradient of the masked mean squared error (host arrays; GPU kernels):
  * grad [LTMP2_MLP_NPARAM], *loss = sum M (out - Y)^2 / sum M. */
 ltmp2_status ltmp2_mlp_grad(const float* params, const float* X, const float* Y, const float* M,

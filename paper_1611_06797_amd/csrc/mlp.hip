@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -336,6 +337,70 @@ extern "C" ltmp2_status ltmp2_mlp_forward(const float* params, const float* X, i
           hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return mfail(LTMP2_EDEVICE, "copy back failed");
+  return LTMP2_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free forward pass.  The hidden activations of up to
+// LTMP2_MLP_NOALLOC_MAX_ROWS rows live in `scratch`, a device array of this
+// file that every GPU running the library holds for the life of the process
+// (8 MiB).  Host code never passes the array's name to a kernel: each
+// device's own address of it comes from hipGetSymbolAddress, taken once per
+// device (with that device current) on the entry point's first call there.
+// Both hidden layers are written in full before they are read, so nothing
+// needs clearing between calls; calls that overlap on one GPU share the
+// array and race.
+namespace {
+constexpr int kNoAllocRows = LTMP2_MLP_NOALLOC_MAX_ROWS;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) float scratch[2 * size_t(kNoAllocRows) * kH];
+
+namespace {
+// Device address of this GPU's scratch array (nullptr on failure).
+float* scratch_on_current_device(std::string& err) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    err = "no usable current device";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" ltmp2_status ltmp2_mlp_forward_noalloc(const float* params_dev, const float* X_dev,
+                                                  int n, float* Y_dev, void* hip_stream) {
+  if (!params_dev || !X_dev || !Y_dev) return mfail(LTMP2_EINVAL, "NULL device pointer");
+  if (n < 1 || n > kNoAllocRows)
+    return mfail(LTMP2_EINVAL, "n must be in [1, " + std::to_string(kNoAllocRows) +
+                                   "] for the allocation-free forward pass");
+  std::string err;
+  float* h = scratch_on_current_device(err);
+  if (!h) return mfail(LTMP2_EDEVICE, err);
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  Net net = unpack(params_dev);
+  float* h1 = h;
+  float* h2 = h + size_t(kNoAllocRows) * kH;
+  hipLaunchKernelGGL(k_lin_fwd, dim3(nblk(long(n) * kH)), dim3(256), 0, st, X_dev, n, kIn,
+                     net.W1, net.b1, kH, 1, h1);
+  hipLaunchKernelGGL(k_lin_fwd, dim3(nblk(long(n) * kH)), dim3(256), 0, st, h1, n, kH, net.W2,
+                     net.b2, kH, 1, h2);
+  hipLaunchKernelGGL(k_lin_fwd, dim3(nblk(long(n) * kOut)), dim3(256), 0, st, h2, n, kH, net.W3,
+                     net.b3, kOut, 0, Y_dev);
+  if (hipGetLastError() != hipSuccess) return mfail(LTMP2_EDEVICE, "launch failed");
   return LTMP2_OK;
 }
 

@@ -28,7 +28,7 @@ EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_
             "ltmp2_mlp_last_error", "ltmp2_remez_polish", "ltmp2_batch_create",
             "ltmp2_batch_energy", "ltmp2_batch_info", "ltmp2_batch_group", "ltmp2_batch_cell",
             "ltmp2_batch_destroy", "ltmp2_batch_last_error", "ltmp2_batch_set_timing",
-            "ltmp2_batch_get_timing", "ltmp2_real_orbitals")
+            "ltmp2_batch_get_timing", "ltmp2_real_orbitals", "ltmp2_mlp_forward_noalloc")
 MLP_NPARAM = 5976
 STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
 
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH):
     lib.ltmp2_batch_last_error.argtypes = [vp]
     lib.ltmp2_batch_last_error.restype = C.c_char_p
     lib.ltmp2_real_orbitals.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, vp, vp]
+    lib.ltmp2_mlp_forward_noalloc.argtypes = [vp, vp, C.c_int, vp, vp]
     lib.ltmp2_mlp_last_error.argtypes = []
     lib.ltmp2_mlp_last_error.restype = C.c_char_p
     for name in ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
@@ -132,7 +133,8 @@ def load(path: str = LIB_PATH):
                  "ltmp2_mlp_grad", "ltmp2_mlp_train", "ltmp2_learned_quadrature",
                  "ltmp2_batch_create", "ltmp2_batch_energy", "ltmp2_batch_info",
                  "ltmp2_batch_group", "ltmp2_batch_cell", "ltmp2_batch_set_timing",
-                 "ltmp2_batch_get_timing", "ltmp2_real_orbitals"):
+                 "ltmp2_batch_get_timing", "ltmp2_real_orbitals",
+                 "ltmp2_mlp_forward_noalloc"):
         getattr(lib, name).restype = C.c_int
     lib.ltmp2_supported_grids.restype = C.c_int
     _lib = lib
@@ -218,6 +220,19 @@ def mlp_forward(params, X):
     _mcheck(lib, lib.ltmp2_mlp_forward(_ptr(np.ascontiguousarray(params, np.float32)), _ptr(X),
                                        X.shape[0], _ptr(out), C.c_void_p(_current_stream())))
     return out
+
+
+MLP_NOALLOC_MAX_ROWS = 16384
+
+
+def mlp_forward_noalloc(params_dev, X_dev, Y_dev, n=None, stream=None):
+    """Network outputs on device tensors (float32: params [5976], X [n, 3], Y [n, 24])
+    through the allocation-free entry point; enqueued on the stream, not synchronised."""
+    lib = load()
+    n = X_dev.shape[0] if n is None else int(n)
+    st = _current_stream() if stream is None else stream
+    _mcheck(lib, lib.ltmp2_mlp_forward_noalloc(_dptr(params_dev), _dptr(X_dev), n,
+                                               _dptr(Y_dev), C.c_void_p(st)))
 
 
 def mlp_grad(params, X, Y, M):
