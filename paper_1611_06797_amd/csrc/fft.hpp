@@ -4,11 +4,12 @@
 // and the Fock-like pair products (forward), and both passes of the double
 // Fourier transform of chi.
 //
-// One thread owns one line of N complex values in registers.  The transform
-// is a decimation-in-time recursion N = R * M with R the leading radix, all
-// loops unrolled at compile time, and twiddles that are compile-time
-// constants (own constexpr sine/cosine: octant reduction plus Taylor series,
-// exact zeros and symmetric values at the multiples of pi/4).
+// One thread owns one line of N complex values in registers.  Lengths with
+// coprime factors use the prime-factor algorithm (no twiddles between the
+// factors); prime powers a decimation-in-time recursion N = R * M with R the
+// leading radix.  All loops are unrolled at compile time, and twiddles are
+// compile-time constants (own constexpr sine/cosine: octant reduction plus
+// Taylor series, exact zeros and symmetric values at the multiples of pi/4).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -108,6 +109,24 @@ constexpr int lead_radix(int n) {
   return (n % 4 == 0 && n != 8) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : (n % 5 == 0) ? 5 : n;
 }
 
+// Coprime split n = n1 * n2 for the prime-factor algorithm: n1 is the largest
+// power of 2 dividing n, else the power of 3; 0 if n is a prime power.
+constexpr int pfa_first(int n) {
+  int p2 = 1;
+  while (n % (2 * p2) == 0) p2 *= 2;
+  if (p2 > 1 && p2 < n) return p2;
+  int p3 = 1;
+  while (n % (3 * p3) == 0) p3 *= 3;
+  if (p3 > 1 && p3 < n) return p3;
+  return 0;
+}
+// inverse of a modulo m (a, m coprime), by search (compile time only)
+constexpr int inv_mod(int a, int m) {
+  for (int t = 1; t < m; ++t)
+    if ((a * t) % m == 1) return t;
+  return m == 1 ? 0 : -1;
+}
+
 // ---- small DFT kernels ------------------------------------------------------
 template <class T, int S, int R>
 struct Dft;
@@ -134,10 +153,10 @@ struct Dft<T, S, 3> {
     cplx<T> t1 = cadd(a[1], a[2]);
     cplx<T> t2 = csub(a[1], a[2]);
     cplx<T> m = {a[0].x + c * t1.x, a[0].y + c * t1.y};
-    cplx<T> r = {-s * t2.y, s * t2.x};  // i s t2
     a[0] = cadd(a[0], t1);
-    a[1] = cadd(m, r);
-    a[2] = csub(m, r);
+    // m +- i s t2, each component one fused multiply-add
+    a[1] = {m.x - s * t2.y, m.y + s * t2.x};
+    a[2] = {m.x + s * t2.y, m.y - s * t2.x};
   }
 };
 
@@ -178,13 +197,38 @@ struct Dft<T, S, 5> {
   }
 };
 
-// ---- recursive decimation in time --------------------------------------------
+// ---- recursive transforms ---------------------------------------------------
+// Sizes with coprime factors n = n1 n2 use the prime-factor algorithm (Good
+// 1958, Thomas 1963): input index (n2 i1 + n1 i2) mod n, output index
+// (n2 <n2^-1>_{n1} k1 + n1 <n1^-1>_{n2} k2) mod n, and the n-point DFT becomes
+// n2 DFTs of length n1 followed by n1 DFTs of length n2 with no twiddle
+// factors in between.  Prime powers use decimation in time:
 // X[k' + M q] = sum_r W_R^{r q} (W_N^{r k'} Y_r[k']),  Y_r = FFT_M(x[m R + r]).
 template <class T, int S, int N>
 struct Fft {
   static LT_HD void run(cplx<T>* x) {
     constexpr int R = lead_radix(N);
-    if constexpr (R == N) {
+    constexpr int N1 = pfa_first(N);
+    if constexpr (N1 > 0) {
+      constexpr int N2 = N / N1;
+      constexpr int T1 = inv_mod(N2 % N1, N1), T2 = inv_mod(N1 % N2, N2);
+      cplx<T> y[N1][N2];
+#pragma unroll
+      for (int i2 = 0; i2 < N2; ++i2) {
+        cplx<T> t[N1];
+#pragma unroll
+        for (int i1 = 0; i1 < N1; ++i1) t[i1] = x[(N2 * i1 + N1 * i2) % N];
+        Fft<T, S, N1>::run(t);
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) y[k1][i2] = t[k1];
+      }
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) {
+        Fft<T, S, N2>::run(y[k1]);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) x[(N2 * T1 * k1 + N1 * T2 * k2) % N] = y[k1][k2];
+      }
+    } else if constexpr (R == N) {
       Dft<T, S, N>::run(x);
     } else {
       constexpr int M = N / R;

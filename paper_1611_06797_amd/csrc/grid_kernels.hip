@@ -68,6 +68,11 @@ ltmp2_status launch(K kern, dim3 grid, size_t lds, hipStream_t st, auto... args)
 // leave room for only one wave per SIMD.  (FP64 registers do not fit two
 // 512-thread waves per SIMD; FP64 keeps 256 threads.)
 constexpr int kWideNT = 512, kWideOpt = 9;
+// Slab tile cap of the wide form: on the 36 grid an 18-plane slab (648 z
+// lines, two rounds of the 512 threads) halves the slab groups against 12
+// planes and fills 378 of the threads in the y pass instead of 252; measured
+// 11 % faster (one workgroup per CU either way: the registers bind first).
+constexpr int kWideTile = 18;
 constexpr int kNarrowNT = 192;
 
 template <template <int> class F>
@@ -219,7 +224,7 @@ ltmp2_status pair(const T* psi, long ld, const cplx<T>* w, int no, const int* pa
   if constexpr (sizeof(T) == sizeof(float)) {
     if (ng > 9 * kThreads) {
       if (ng > kWideOpt * kWideNT) return LTMP2_EINVAL;
-      return pair_km<T, kWideNT, kWideOpt>(pc, choose_sx_fwd<T>(2 * kmax + 1, 12), st);
+      return pair_km<T, kWideNT, kWideOpt>(pc, choose_sx_fwd<T>(2 * kmax + 1, kWideTile), st);
     }
   }
   return by_opt<PairF<T>::template F>(ng, pc, choose_sx_fwd<T>(2 * kmax + 1), st);
@@ -268,7 +273,8 @@ ltmp2_status pair_multi(const PairCell* cells, const long* prefix, int ncells, i
                         int kmax_max, int kfix, int sx, int nblocks, hipStream_t st) {
   if constexpr (sizeof(T) == sizeof(float)) {
     if (ng_max > 9 * kThreads) {
-      if (ng_max > kWideOpt * kWideNT || sx < 1 || N % sx != 0 || sx > 12) return LTMP2_EINVAL;
+      if (ng_max > kWideOpt * kWideNT || sx < 1 || N % sx != 0 || sx > kWideTile)
+        return LTMP2_EINVAL;
       return pair_multi_km<T, kWideNT, kWideOpt>(kfix, cells, prefix, ncells, kmax_max, sx,
                                                   nblocks, st);
     }

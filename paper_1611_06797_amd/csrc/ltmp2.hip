@@ -449,11 +449,13 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
       }
     }
   }
-  // pairs i <= j in 8 x 8 blocks of (i, j): the workgroups resident on one
-  // XCD take consecutive items, and a block touches 16 orbitals and 16
-  // transformed states, which stay in that XCD's L2
+  // pairs i <= j in blocks of (i, j): the workgroups resident on one XCD take
+  // consecutive items and share the block's orbitals and transformed states
+  // in that XCD's L2 and the Infinity Cache.  8 x 8 blocks; 16 x 16 for the
+  // wide 512-thread pair form (auxiliary sets above 2304 vectors), measured
+  // 2 % faster there.
   std::vector<int> pairs;
-  constexpr int kPairBlock = 8;
+  const int kPairBlock = (P.prec != LTMP2_FP64 && c->ng > 9 * kThreads) ? 16 : 8;
   for (int bi = 0; bi < c->no; bi += kPairBlock)
     for (int bj = bi; bj < c->no; bj += kPairBlock)
       for (int i = bi; i < std::min(bi + kPairBlock, c->no); ++i)

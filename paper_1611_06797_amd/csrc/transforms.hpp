@@ -100,8 +100,10 @@ __host__ __device__ constexpr int kwin(int n) { return (n - 1) / 3; }
 // auxiliary window kwin(N), an alias-free grid allows k_orb <= korb_win(N).
 __host__ __device__ constexpr int korb_win(int n) { return (n - 1 - kwin(n)) / 2; }
 
-// Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10, 12).
+// Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10, 12,
+// 18).
 __host__ __device__ constexpr int slab_tile_at_most(int n, int cap) {
+  if (cap >= 18 && n % 18 == 0) return 18;
   for (int d = cap < 12 ? cap : 12; d > 1; --d)
     if (d != 7 && d != 11 && n % d == 0) return d;
   return 1;
@@ -155,6 +157,7 @@ __device__ inline void column_fft_rows(cplx<T>* a, int nk, int R, int pstride) {
 
 template <class T, int S, int N, int NT = kThreads>
 __device__ inline void column_fft_rows_tile(cplx<T>* a, int d, int nk, int R, int pstride) {
+  if constexpr (N % 18 == 0) if (d == 18) return column_fft_rows<T, S, 18, NT>(a, nk, R, pstride);
   if constexpr (N % 12 == 0) if (d == 12) return column_fft_rows<T, S, 12, NT>(a, nk, R, pstride);
   if constexpr (N % 10 == 0) if (d == 10) return column_fft_rows<T, S, 10, NT>(a, nk, R, pstride);
   if constexpr (N % 9 == 0) if (d == 9) return column_fft_rows<T, S, 9, NT>(a, nk, R, pstride);
