@@ -168,3 +168,51 @@ def test_full_batch_sampled_cells():
             e1, x1, _, _ = ctx.energy()
         tol = s.n_occ * 1e-6
         assert abs(ed[k] - e1) < tol and abs(ex[k] - x1) < tol, k
+
+
+@pytest.mark.parametrize("prec_name", ["bf16x3", "fp64"])
+def test_full_batch_against_stored_oracle_cells(prec_name):
+    # the whole 64-cell batch, with the oracle's quadrature given for the
+    # cells that tests/golden/make_batch_cells.py stored (one or two per
+    # internal transform grid 12, 15, 18, 20, 24): those cells against the
+    # oracle; the 24-grid group's pair launches run 192-thread workgroups
+    # (slab groups of 129..192 z lines)
+    import json
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    path = os.path.join(os.path.dirname(__file__), "golden", "batch_cells.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet")
+    from paper_1611_06797_amd import Batch, BF16X3, FP64
+    ref = {c["index"]: c for c in json.load(open(path))["cells"]}
+    specs = batch_specs()
+    _say(f"full 64-cell batch ({prec_name}) vs stored oracle cells {sorted(ref)}")
+    cells = []
+    for k, s in enumerate(specs):
+        m, e, c = make_cell(s)
+        r = ref.get(k)
+        cells.append(dict(L=s.L, n_fft=s.n, ecut=s.ecut, eaux=s.eaux, miller=m, eps=e, coeff=c,
+                          n_occ=s.n_occ, n_tau=s.n_tau,
+                          tau=None if r is None else np.array(r["tau"]),
+                          w=None if r is None else np.array(r["w"])))
+    prec = BF16X3 if prec_name == "bf16x3" else FP64
+    with Batch(cells, prec=prec) as b:
+        ed, ex = b.energy()
+        st = b.stats()
+        groups = [b.group(g) for g in range(st.n_groups)]
+        grids = {k: b.cell_info(k).n_grid for k in ref}
+    print("[batch groups]", groups, flush=True)
+    for k, r in ref.items():
+        assert grids[k] == r["internal_grid"], k
+        dd, dx = ed[k] - r["e_d_lt"], ex[k] - r["e_x_lt"]
+        print(f"[batch {prec_name} cell {k} grid {grids[k]}] dE_d={dd:.3e} dE_x={dx:.3e}",
+              flush=True)
+        assert abs(dd) < r["n_occ"] * 1e-6 and abs(dx) < r["n_occ"] * 1e-6, k
+        if prec == FP64:
+            assert abs(dd) <= 1e-9 * abs(r["e_d_lt"]) and abs(dx) <= 1e-9 * abs(r["e_x_lt"]), k
+    g24 = [g for g in groups if g["n_fft"] == 24]
+    assert len(g24) == 1
+    if prec == BF16X3:
+        assert 128 < 24 * g24[0]["slab_tile"] <= 192
