@@ -402,6 +402,9 @@ def main():
         step(k)
         if args.step_unit == "energy" or (k + 1) % nt == 0:
             log(f"step {k}: E_d={w_used @ per_tau[:, 0]:.10f} E_x={w_used @ per_tau[:, 1]:.10f}")
+        else:
+            log(f"step {k}: tau_{k % nt} E_d(tau)={per_tau[k % nt, 0]:.10f} "
+                f"E_x(tau)={per_tau[k % nt, 1]:.10f}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     timing = ctx.get_timing()
@@ -428,10 +431,15 @@ def main():
                         stream=stream.cuda_stream, prec=0, tau=tau_used, w=w_used)
         torch.cuda.synchronize()
         log(f"fp64 setup {time.time() - t:.1f}s")
+        # one full energy, one Laplace point at a time (a progress line per point)
+        pt64 = np.zeros((nt, 2))
         t1 = time.perf_counter()
-        ed64, ex64, pt64, _ = ctx64.energy()
+        for it in range(nt):
+            pt64[it] = (ctx64.chi(it), ctx64.exchange(it))
+            log(f"fp64 point {it}: {time.perf_counter() - t1:.1f}s")
         torch.cuda.synchronize()
         dt64 = time.perf_counter() - t1
+        ed64, ex64 = float(w_used @ pt64[:, 0]), float(w_used @ pt64[:, 1])
         ctx64.close()
         tol = spec.n_occ * 1e-6
         ref = {"fp64_energies_per_s": 1.0 / dt64, "fp64_seconds_per_energy": dt64,
