@@ -87,6 +87,12 @@ typedef struct {
   int prec;             /* ltmp2_precision                                      */
   size_t workspace_cap; /* bytes; 0 = no cap.  Setup fails with LTMP2_ENOMEM if
                            the device footprint would exceed it                 */
+  int n_extrap;         /* internal cutoff extrapolation (Implementation section,
+                           "Internal cutoff extrapolation"): 0 = off, else the
+                           number n_c (2..8) of nested auxiliary cutoffs
+                           eaux / extrap_alpha^(n-1), n = 1..n_c, evaluated in
+                           the same pass (ltmp2_get_extrapolation)              */
+  double extrap_alpha;  /* ratio of consecutive cutoffs, > 1 (0: 1.05)         */
 } ltmp2_params;
 
 /* Sizes of a prepared context. */
@@ -186,6 +192,25 @@ ltmp2_status ltmp2_exchange(ltmp2_ctx* ctx, int itau, int g_first, int g_count,
  */
 ltmp2_status ltmp2_energy(ltmp2_ctx* ctx, double* e_direct, double* e_exchange,
                           double* per_tau, double* quad_err);
+
+/*
+ * Internal cutoff extrapolation (Implementation section, "Internal cutoff
+ * extrapolation"; Eq. CutDecay), available after ltmp2_energy on a context
+ * set up with n_extrap = n_c > 0.  During the energy every Coulomb-weighted
+ * (G, G') sum is also split by the nested auxiliary spheres
+ * |G|^2 / 2 <= eaux / alpha^(n-1), n = 1..n_c: a term counts for sphere n iff
+ * both vectors lie in it, which gives the energy of every smaller auxiliary
+ * cutoff exactly (the orbitals, overlap densities and quadrature do not
+ * depend on it).  The energies are then fitted by E[n] = a + b eaux[n]^(-3/2)
+ * (least squares, FP64); a is the extrapolated energy.
+ *   e_aux      [n_c]  the cutoffs eaux[n] (Ha)              (may be NULL)
+ *   e_direct   [n_c]  E_d at each cutoff (Ha; e_direct[0] = ltmp2_energy's)
+ *   e_exchange [n_c]  E_x at each cutoff                     (may be NULL)
+ *   e_inf      [3]    intercepts of E_d + E_x, E_d and E_x   (may be NULL)
+ * LTMP2_ESTATE if the context has no extrapolation or no energy yet.
+ */
+ltmp2_status ltmp2_get_extrapolation(const ltmp2_ctx* ctx, double* e_aux, double* e_direct,
+                                     double* e_exchange, double* e_inf);
 
 /* Quadrature in use: tau, w [n_tau] (host), may be NULL. */
 ltmp2_status ltmp2_get_quadrature(const ltmp2_ctx* ctx, double* tau, double* w, double* delta);

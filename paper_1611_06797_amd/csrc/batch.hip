@@ -279,6 +279,10 @@ extern "C" ltmp2_status ltmp2_batch_create(int n_cells, const ltmp2_params* para
   std::vector<const double*> cuse(n_cells);
   for (int k = 0; k < n_cells; ++k) {
     if (params[k].prec != prec) return bfail(nullptr, LTMP2_EINVAL, "cells differ in precision");
+    if (params[k].n_extrap)
+      return bfail(nullptr, LTMP2_EINVAL,
+                   "cell " + std::to_string(k) +
+                       ": the cutoff extrapolation runs per context (ltmp2_setup), not batched");
     ltmp2_status s = validate_inputs(&params[k], miller[k], eps[k], coeff[k],
                                      tau ? tau[k] : nullptr, w ? w[k] : nullptr, creal[k],
                                      &cuse[k]);

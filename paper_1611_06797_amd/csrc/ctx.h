@@ -60,6 +60,18 @@ struct ltmp2_ctx {
   double* d_xpart = nullptr;   // [nh][npairs]
   double* d_xrow = nullptr;    // [nh] v(G') times the row sums of d_xpart
   double* d_scal = nullptr;    // [2 * ntau + 8] device scalars
+  // internal cutoff extrapolation: nb nested auxiliary spheres (0 = off)
+  int nb = 0;
+  double alpha = 1.05;
+  std::vector<double> eaux_n;    // [nb] cutoffs eaux / alpha^(n-1)
+  signed char* d_shell = nullptr;  // [ng] spheres containing each vector
+  double* d_pdb = nullptr;     // [nh][nb] direct-term bins per G'
+  double* d_xb = nullptr;      // [nh][npairs][nb] exchange bins per (G', pair)
+  double* d_xrowb = nullptr;   // [nh][nb]
+  double* d_scalb = nullptr;   // [ntau][2][nb] per-tau bin sums (E_d, E_x)
+  bool ext_valid = false;
+  std::vector<double> ext_d, ext_x;  // [nb] energies per cutoff (last ltmp2_energy)
+  double ext_inf[3] = {0, 0, 0};
 
   std::vector<void*> owned;
   size_t bytes = 0;

@@ -28,13 +28,15 @@ struct GridOps {
                            double dV, cplx<T>* chihat, hipStream_t st);
   ltmp2_status (*chi_cols)(const cplx<T>* chihat, long ld, const int* gdesc, int ng, int nh,
                            const double* v, int kmax, double dV, double* pd,
-                           cplx<double>* chi_out, hipStream_t st);
+                           cplx<double>* chi_out, ShellBins bins, hipStream_t st);
   ltmp2_status (*wstates)(const T* P, int npw, const int* wq, const signed char* wsgn,
                           SphereCols sc, int nitems, double scale, cplx<T>* w, long ld,
                           hipStream_t st);
+  // shell / xbins / nb / g0: optional split by auxiliary cutoff shell (PairCell)
   ltmp2_status (*pair)(const T* psi, long ld, const cplx<T>* w, int no, const int* pairs,
                        int npairs, int gb, const int* gdesc, int ng, const double* v, int kmax,
-                       double dV2, double* xpart, hipStream_t st);
+                       double dV2, double* xpart, const signed char* shell, double* xbins,
+                       int nb, int g0, hipStream_t st);
   // persistent multi-cell pair launch (device arrays cells[ncells], prefix[ncells + 1]);
   // all cells share the kept-set instance kfix (pair_kept)
   ltmp2_status (*pair_multi)(const PairCell* cells, const long* prefix, int ncells, int ng_max,
@@ -80,5 +82,13 @@ __global__ void k_reduce_direct(const double* pd, int nh, double* out);
 __global__ void k_reduce_xrows(const double* xpart, int g0, int npairs, const double* v,
                                double* xrow);
 __global__ void k_reduce_exchange(const double* xrow, int g0, int gcount, double* out);
+// The same three reductions per auxiliary cutoff shell bin (ShellBins):
+//   out[b] = -4 sum_g pdb[g][b];  xrowb[g][b] = v[g] sum_p xb[g][p][b];
+//   out[b] = 2 sum_{g in range} xrowb[g][b]
+__global__ void k_reduce_direct_bins(const double* pdb, int nh, int nb, double* out);
+__global__ void k_reduce_xrows_bins(const double* xb, int g0, int npairs, int nb, const double* v,
+                                    double* xrowb);
+__global__ void k_reduce_exchange_bins(const double* xrowb, int g0, int gcount, int nb,
+                                       double* out);
 
 }  // namespace ltmp2

@@ -124,16 +124,19 @@ __global__ __launch_bounds__(kThreads) void k_chi_rows(const T* __restrict__ chi
 //   chi(G, G') = dV sum_r e^{-iG.r} chihat(r, G'),  G in the full set,
 //   pd[g] = v(G') sum_G v(G) |chi(G, G')|^2.
 // Optionally stores chi(G, G') for G' in H and, by chi(-G, -G') =
-// conj chi(G, G') (real chi(r, r')), for G' in -H:  out[G][G'] (ng x ng).
+// conj chi(G, G') (real chi(r, r')), for G' in -H:  out[G][G'] (ng x ng),
+// and the same sum split by auxiliary cutoff shell (bins.out [n_h][nb]).
 template <class T, int N, int OPT>
 __global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict__ chihat, long ld,
                                                        const int* __restrict__ gdesc_all, int ng,
                                                        int nh, const double* __restrict__ v,
                                                        int kmax, int sx, double dV,
                                                        double* __restrict__ pd,
-                                                       cplx<double>* __restrict__ chi_out) {
+                                                       cplx<double>* __restrict__ chi_out,
+                                                       ShellBins bins) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[kThreads / 64];
+  __shared__ double redb[kThreads / 64 * kMaxShells];
   const int nk = 2 * kmax + 1;
   SlabLds<T> L = fwd_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, -1, N>(L.tw);
@@ -151,12 +154,16 @@ __global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict
   auto ld_ = [&](int, int x, int y, int z) { return col[(x * N + z) * N + y]; };
   forward_pruned<T, -1, N, 1, OPT>(ld_, 1, kmax, sx, gd, ng, acc, L);
   double s = 0.0;
+  double sb[kMaxShells] = {};
+  const int sg = bins.shell ? bins.shell[g] : 0;
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
     const int o = threadIdx.x + t * kThreads;
     if (o < ng) {
       const double re = dV * double(acc[0][t].x), im = dV * double(acc[0][t].y);
-      s += v[o] * (re * re + im * im);
+      const double term = v[o] * (re * re + im * im);
+      s += term;
+      if (bins.shell) bin_add(sb, min(int(bins.shell[o]), sg) - 1, term);
       if (chi_out) {
         const int on = (o < nh) ? o + nh : o - nh;
         chi_out[long(o) * ng + g] = {re, im};
@@ -166,6 +173,11 @@ __global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) pd[g] = v[g] * s;
+  if (bins.shell) {
+    block_sum_bins(sb, redb);
+    if (threadIdx.x == 0)
+      for (int b = 0; b < bins.nb; ++b) bins.out[long(g) * bins.nb + b] = v[g] * sb[b];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -230,15 +242,22 @@ struct PairCell {
   long ld;
   int nocc, npairs, gb, ng, kmax;
   double dV2;
+  // optional split by auxiliary cutoff shell (ShellBins): shell [ng], the
+  // block's first outer vector g0 (shell of G' = shell[g0 + gl]) and
+  // xbins [gb][npairs][nb] (nullptr: no split)
+  const signed char* shell = nullptr;
+  double* xbins = nullptr;
+  int nb = 0, g0 = 0;
 };
 
 // KM >= 0: the cell's kept set is kmax = KM, known at compile time (see kwin);
-// KM = -1: runtime kmax.
-template <class T, int N, int OPT, int NT = kThreads, int KM = -1>
+// KM = -1: runtime kmax.  JOINT: both fields side by side in two slab
+// buffers (forward_pruned_joint; shared memory fwd2_lds_bytes).
+template <class T, int N, int OPT, int NT = kThreads, int KM = -1, bool JOINT = false>
 __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void* smem,
                                  double* red) {
   const int nk = 2 * (KM >= 0 ? KM : pc.kmax) + 1;
-  SlabLds<T> L = fwd_lds<T>(smem, N, nk, sx);
+  SlabLds<T> L = JOINT ? fwd2_lds<T>(smem, N, nk, sx) : fwd_lds<T>(smem, N, nk, sx);
   fill_twiddles<T, -1, N>(L.tw);
   const int i = pc.pairs[p] & 0xffff, j = pc.pairs[p] >> 16;
   const T* psi = static_cast<const T*>(pc.psi);
@@ -263,31 +282,47 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
     const cplx<T> b = (f == 0) ? wj[r] : wi[r];
     return cplx<T>{a * b.x, a * b.y};
   };
-  forward_pruned<T, -1, N, 2, OPT, NT, KM>(ld_, (i == j) ? 1 : 2, pc.kmax, sx, gd, pc.ng, acc,
-                                           L);
+  if constexpr (JOINT)
+    forward_pruned_joint<T, -1, N, OPT, NT, KM>(ld_, (i == j) ? 1 : 2, pc.kmax, sx, gd, pc.ng, acc,
+                                                L);
+  else
+    forward_pruned<T, -1, N, 2, OPT, NT, KM>(ld_, (i == j) ? 1 : 2, pc.kmax, sx, gd, pc.ng, acc,
+                                             L);
   double s = 0.0;
+  double sb[kMaxShells] = {};
+  const int sg = pc.shell ? pc.shell[pc.g0 + gl] : 0;
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
     const int o = threadIdx.x + t * NT;
     if (o < pc.ng) {
       const double ar = acc[0][t].x, ai = acc[0][t].y;
+      double term;
       if (i == j) {
-        s += pc.v[o] * (ar * ar + ai * ai);
+        term = pc.v[o] * (ar * ar + ai * ai);
       } else {
         const double br = acc[1][t].x, bi = acc[1][t].y;
-        s += 2.0 * pc.v[o] * (ar * br + ai * bi);
+        term = 2.0 * pc.v[o] * (ar * br + ai * bi);
       }
+      s += term;
+      if (pc.shell) bin_add(sb, min(int(pc.shell[o]), sg) - 1, term);
     }
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) pc.xpart[long(gl) * pc.npairs + p] = pc.dV2 * s;
+  if (pc.shell) {
+    __shared__ double redb[NT / 64 * kMaxShells];
+    block_sum_bins(sb, redb);
+    if (threadIdx.x == 0)
+      for (int b = 0; b < pc.nb; ++b)
+        pc.xbins[(long(gl) * pc.npairs + p) * pc.nb + b] = pc.dV2 * sb[b];
+  }
 }
 
 // One cell: workgroups are dispatched round-robin over the 8 XCDs; each XCD
 // gets a contiguous range of the (G', pair) list, whose pairs come in 8 x 8
 // blocks of (i, j), so the workgroups resident on one XCD share a handful of
 // psi_i and w_j^{(G')} in that XCD's L2.
-template <class T, int N, int OPT, int NT = kThreads, int KM = -1>
+template <class T, int N, int OPT, int NT = kThreads, int KM = -1, bool JOINT = false>
 __global__ __launch_bounds__(NT) void k_pair(PairCell pc, int sx) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[NT / 64];
@@ -296,7 +331,7 @@ __global__ __launch_bounds__(NT) void k_pair(PairCell pc, int sx) {
   const long t = long(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= total) return;
   const int gl = int(t / pc.npairs);
-  pair_item<T, N, OPT, NT, KM>(pc, gl, int(t - long(gl) * pc.npairs), sx, smem, red);
+  pair_item<T, N, OPT, NT, KM, JOINT>(pc, gl, int(t - long(gl) * pc.npairs), sx, smem, red);
 }
 
 // Several cells of the same grid in one persistent launch: the work list is

@@ -119,6 +119,11 @@ ltmp2_status validate(const ltmp2_params* p, const int32_t* miller, const double
   if (p->quad_mode < 0 || p->quad_mode > 2) return fail(nullptr, LTMP2_EINVAL, "unknown quad_mode");
   if (p->quad_mode == LTMP2_QUAD_LEARNED && p->n_tau > 12)
     return fail(nullptr, LTMP2_EINVAL, "learned quadrature covers n_tau <= 12");
+  if (p->n_extrap < 0 || p->n_extrap == 1 || p->n_extrap > kMaxShells)
+    return fail(nullptr, LTMP2_EINVAL, "n_extrap must be 0 or in [2, 8]");
+  if (p->n_extrap && p->extrap_alpha != 0.0 &&
+      !(p->extrap_alpha > 1.0 && std::isfinite(p->extrap_alpha)))
+    return fail(nullptr, LTMP2_EINVAL, "extrap_alpha must be > 1 (or 0 for 1.05)");
   if (!miller || !eps || !coeff) return fail(nullptr, LTMP2_EINVAL, "NULL input array");
   if (p->quad_mode == LTMP2_QUAD_GIVEN) {
     if (!tau || !w) return fail(nullptr, LTMP2_EINVAL, "tau and w required with LTMP2_QUAD_GIVEN");
@@ -371,6 +376,28 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
     v[k] = 4.0 * M_PI / (c->omega * b * b * double(x * x + y * y + z * z));
   }
 
+  // internal cutoff extrapolation: number of nested spheres containing each
+  // auxiliary vector (the same inclusive integer test as the auxiliary set)
+  std::vector<signed char> shell;
+  if (P.n_extrap > 0) {
+    c->nb = P.n_extrap;
+    c->alpha = P.extrap_alpha > 0.0 ? P.extrap_alpha : 1.05;
+    c->eaux_n.resize(c->nb);
+    std::vector<int> lims(c->nb);
+    for (int q = 0; q < c->nb; ++q) {
+      c->eaux_n[q] = P.eaux / std::pow(c->alpha, q);
+      lims[q] = int(std::floor(2.0 * c->eaux_n[q] / (b * b) + 1e-9));
+    }
+    shell.resize(c->ng);
+    for (int k = 0; k < c->ng; ++k) {
+      const int x = c->aux[3 * k], y = c->aux[3 * k + 1], z = c->aux[3 * k + 2];
+      const int m2 = x * x + y * y + z * z;
+      int sh = 0;
+      while (sh < c->nb && m2 <= lims[sh]) ++sh;
+      shell[k] = static_cast<signed char>(sh);
+    }
+  }
+
   // orbital sphere in (ky, kz) column order
   int ko = 0;
   for (int k = 0; k < c->npw; ++k)
@@ -510,6 +537,9 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
                        size_t(c->nv) * c->ldbpw + nrp * nrp + 2 * size_t(c->nh) * nrp) +
                  sizeof(double) * (size_t(c->nh) + size_t(c->nh) * c->npairs) +
                  sizeof(double) * 2 * size_t(c->nst) * c->npw;
+  if (c->nb)
+    fixed += sizeof(double) * size_t(c->nb) *
+             (2 * size_t(c->nh) + size_t(c->nh) * c->npairs + 2 * size_t(c->ntau));
   if (P.prec == LTMP2_BF16X3) {
     c->kpo = (c->no + 63) / 64 * 64;
     c->kpv = (c->nv + 63) / 64 * 64;
@@ -575,6 +605,15 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
     HIPCHK(c, hipMemsetAsync(c->d_b3h, 0, bb, c->stream));
     HIPCHK(c, hipMemsetAsync(c->d_b3l, 0, bb, c->stream));
   }
+  if (c->nb) {
+    if ((s = upload(c, &c->d_shell, shell)) || (s = dalloc(c, &c->d_pdb, size_t(c->nh) * c->nb)) ||
+        (s = dalloc(c, &c->d_xb, size_t(c->nh) * c->npairs * c->nb)) ||
+        (s = dalloc(c, &c->d_xrowb, size_t(c->nh) * c->nb)) ||
+        (s = dalloc(c, &c->d_scalb, 2 * size_t(c->ntau) * c->nb)))
+      return s;
+    HIPCHK(c, hipMemsetAsync(c->d_scalb, 0, sizeof(double) * 2 * size_t(c->ntau) * c->nb,
+                             c->stream));
+  }
   if (P.workspace_cap && c->bytes > P.workspace_cap)
     return fail(nullptr, LTMP2_ENOMEM, "device footprint exceeds the workspace cap");
   HIPCHK(c, hipMemsetAsync(c->d_psi, 0, es * size_t(c->nst) * nrp, c->stream));
@@ -634,14 +673,19 @@ ltmp2_status run_direct_t(ltmp2_ctx* c, int itau, double* chi_out) {
   if (s) return fail(c, s, "chi row transform launch failed");
   {
     StageTimer tm(c, 2);
+    ShellBins bins;
+    if (c->nb) bins = ShellBins{c->d_shell, c->nb, c->d_pdb};
     s = ops->chi_cols(static_cast<const cplx<T>*>(c->d_chihat), c->nrp, c->d_gdesc, c->ng, c->nh,
                       c->d_v, c->kmax_aux, c->dV, c->d_pd,
-                      reinterpret_cast<cplx<double>*>(chi_out), c->stream);
+                      reinterpret_cast<cplx<double>*>(chi_out), bins, c->stream);
   }
   if (s) return fail(c, s, "chi column transform launch failed");
   StageTimer tm(c, 6);
   hipLaunchKernelGGL(k_reduce_direct, dim3(1), dim3(256), 0, c->stream, c->d_pd, c->nh,
                      c->d_scal + 2 * itau);
+  if (c->nb)
+    hipLaunchKernelGGL(k_reduce_direct_bins, dim3(1), dim3(256), 0, c->stream, c->d_pdb, c->nh,
+                       c->nb, c->d_scalb + size_t(2 * itau) * c->nb);
   return check_launch(c, "k_reduce_direct");
 }
 
@@ -696,7 +740,9 @@ ltmp2_status block_pair_t(ltmp2_ctx* c, int g0, int gb) {
   ltmp2_status s = ops->pair(static_cast<const T*>(c->d_psi), c->nrp,
                              static_cast<const cplx<T>*>(c->d_w), c->no, c->d_pairs, c->npairs, gb,
                              c->d_gdesc, c->ng, c->d_v, c->kmax_aux, c->dV * c->dV,
-                             c->d_xpart + size_t(g0) * c->npairs, c->stream);
+                             c->d_xpart + size_t(g0) * c->npairs, c->d_shell,
+                             c->nb ? c->d_xb + size_t(g0) * c->npairs * c->nb : nullptr, c->nb,
+                             g0, c->stream);
   if (s) return fail(c, s, "pair transform launch failed");
   return LTMP2_OK;
 }
@@ -708,6 +754,12 @@ ltmp2_status reduce_x(ltmp2_ctx* c, int itau, int g_first, int g_count) {
                      c->npairs, c->d_v, c->d_xrow);
   hipLaunchKernelGGL(k_reduce_exchange, dim3(1), dim3(256), 0, c->stream, c->d_xrow, g_first,
                      g_count, c->d_scal + 2 * itau + 1);
+  if (c->nb) {
+    hipLaunchKernelGGL(k_reduce_xrows_bins, dim3(g_count), dim3(256), 0, c->stream, c->d_xb,
+                       g_first, c->npairs, c->nb, c->d_v, c->d_xrowb);
+    hipLaunchKernelGGL(k_reduce_exchange_bins, dim3(1), dim3(256), 0, c->stream, c->d_xrowb,
+                       g_first, g_count, c->nb, c->d_scalb + size_t(2 * itau + 1) * c->nb);
+  }
   return check_launch(c, "k_reduce_exchange");
 }
 
@@ -896,6 +948,65 @@ extern "C" ltmp2_status ltmp2_exchange(ltmp2_ctx* c, int itau, int g_first, int 
   return LTMP2_OK;
 }
 
+namespace {
+// least-squares line y = a + b x; returns a
+double line_intercept(const std::vector<double>& x, const std::vector<double>& y) {
+  const double m = double(x.size());
+  double sx = 0, sy = 0, sxx = 0, sxy = 0;
+  for (size_t k = 0; k < x.size(); ++k) {
+    sx += x[k];
+    sy += y[k];
+    sxx += x[k] * x[k];
+    sxy += x[k] * y[k];
+  }
+  const double b = (m * sxy - sx * sy) / (m * sxx - sx * sx);
+  return (sy - b * sx) / m;
+}
+}  // namespace
+
+// Energies of the nested auxiliary cutoffs from the per-tau bin sums (bin b
+// holds the terms whose smaller sphere count is b + 1; cutoff n sums bins
+// n-1 .. nb-1) and their extrapolation in eaux^(-3/2) (Eq. CutDecay).
+static ltmp2_status assemble_extrapolation(ltmp2_ctx* c) {
+  const int nb = c->nb;
+  std::vector<double> bins(2 * size_t(c->ntau) * nb);
+  HIPCHK(c, hipMemcpyAsync(bins.data(), c->d_scalb, sizeof(double) * bins.size(),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->ext_d.assign(nb, 0.0);
+  c->ext_x.assign(nb, 0.0);
+  for (int t = 0; t < c->ntau; ++t)
+    for (int n = 0; n < nb; ++n)
+      for (int q = n; q < nb; ++q) {
+        c->ext_d[n] += c->w[t] * bins[(2 * size_t(t)) * nb + q];
+        c->ext_x[n] += c->w[t] * bins[(2 * size_t(t) + 1) * nb + q];
+      }
+  std::vector<double> x(nb), yt(nb);
+  for (int n = 0; n < nb; ++n) {
+    x[n] = std::pow(c->eaux_n[n], -1.5);
+    yt[n] = c->ext_d[n] + c->ext_x[n];
+  }
+  c->ext_inf[0] = line_intercept(x, yt);
+  c->ext_inf[1] = line_intercept(x, c->ext_d);
+  c->ext_inf[2] = line_intercept(x, c->ext_x);
+  for (double v : c->ext_inf)
+    if (!std::isfinite(v)) return fail(c, LTMP2_ENUMERIC, "non-finite extrapolation");
+  c->ext_valid = true;
+  return LTMP2_OK;
+}
+
+extern "C" ltmp2_status ltmp2_get_extrapolation(const ltmp2_ctx* c, double* e_aux,
+                                                double* e_direct, double* e_exchange,
+                                                double* e_inf) {
+  if (!c) return LTMP2_EINVAL;
+  if (!c->nb || !c->ext_valid) return LTMP2_ESTATE;
+  if (e_aux) std::copy(c->eaux_n.begin(), c->eaux_n.end(), e_aux);
+  if (e_direct) std::copy(c->ext_d.begin(), c->ext_d.end(), e_direct);
+  if (e_exchange) std::copy(c->ext_x.begin(), c->ext_x.end(), e_exchange);
+  if (e_inf) std::copy(c->ext_inf, c->ext_inf + 3, e_inf);
+  return LTMP2_OK;
+}
+
 extern "C" ltmp2_status ltmp2_energy(ltmp2_ctx* c, double* e_direct, double* e_exchange,
                                      double* per_tau, double* quad_err) {
   ltmp2_status s = usable(c, 0);
@@ -914,6 +1025,7 @@ extern "C" ltmp2_status ltmp2_energy(ltmp2_ctx* c, double* e_direct, double* e_e
     ex += c->w[t] * pt[2 * t + 1];
   }
   if (!std::isfinite(ed) || !std::isfinite(ex)) return fail(c, LTMP2_ENUMERIC, "non-finite energy");
+  if (c->nb && (s = assemble_extrapolation(c))) return s;
   if (e_direct) *e_direct = ed;
   if (e_exchange) *e_exchange = ex;
   if (per_tau) std::copy(pt.begin(), pt.end(), per_tau);

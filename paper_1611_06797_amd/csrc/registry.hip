@@ -163,4 +163,39 @@ __global__ void k_reduce_exchange(const double* xrow, int g0, int gcount, double
   if (threadIdx.x == 0) out[0] = 2.0 * s;
 }
 
+__global__ void k_reduce_direct_bins(const double* pdb, int nh, int nb, double* out) {
+  __shared__ double red[4 * kMaxShells];
+  double sb[kMaxShells] = {};
+  for (int g = threadIdx.x; g < nh; g += blockDim.x)
+    for (int b = 0; b < nb; ++b) bin_add(sb, b, pdb[long(g) * nb + b]);
+  block_sum_bins(sb, red);
+  if (threadIdx.x == 0)
+    for (int b = 0; b < nb; ++b) out[b] = -4.0 * sb[b];
+}
+
+// one block per G': xrowb[g][b] = v(G') sum_p xb[g][p][b]
+__global__ void k_reduce_xrows_bins(const double* xb, int g0, int npairs, int nb, const double* v,
+                                    double* xrowb) {
+  __shared__ double red[4 * kMaxShells];
+  const int g = g0 + blockIdx.x;
+  const double* row = xb + size_t(g) * npairs * nb;
+  double sb[kMaxShells] = {};
+  for (int p = threadIdx.x; p < npairs; p += blockDim.x)
+    for (int b = 0; b < nb; ++b) bin_add(sb, b, row[long(p) * nb + b]);
+  block_sum_bins(sb, red);
+  if (threadIdx.x == 0)
+    for (int b = 0; b < nb; ++b) xrowb[long(g) * nb + b] = v[g] * sb[b];
+}
+
+__global__ void k_reduce_exchange_bins(const double* xrowb, int g0, int gcount, int nb,
+                                       double* out) {
+  __shared__ double red[4 * kMaxShells];
+  double sb[kMaxShells] = {};
+  for (int g = g0 + threadIdx.x; g < g0 + gcount; g += blockDim.x)
+    for (int b = 0; b < nb; ++b) bin_add(sb, b, xrowb[long(g) * nb + b]);
+  block_sum_bins(sb, red);
+  if (threadIdx.x == 0)
+    for (int b = 0; b < nb; ++b) out[b] = 2.0 * sb[b];
+}
+
 }  // namespace ltmp2

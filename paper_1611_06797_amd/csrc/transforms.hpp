@@ -100,10 +100,8 @@ __host__ __device__ constexpr int kwin(int n) { return (n - 1) / 3; }
 // auxiliary window kwin(N), an alias-free grid allows k_orb <= korb_win(N).
 __host__ __device__ constexpr int korb_win(int n) { return (n - 1 - kwin(n)) / 2; }
 
-// Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10, 12,
-// 18).
+// Largest slab tile d <= cap that divides n (tiles are 1..6, 8, 9, 10, 12).
 __host__ __device__ constexpr int slab_tile_at_most(int n, int cap) {
-  if (cap >= 18 && n % 18 == 0) return 18;
   for (int d = cap < 12 ? cap : 12; d > 1; --d)
     if (d != 7 && d != 11 && n % d == 0) return d;
   return 1;
@@ -157,7 +155,6 @@ __device__ inline void column_fft_rows(cplx<T>* a, int nk, int R, int pstride) {
 
 template <class T, int S, int N, int NT = kThreads>
 __device__ inline void column_fft_rows_tile(cplx<T>* a, int d, int nk, int R, int pstride) {
-  if constexpr (N % 18 == 0) if (d == 18) return column_fft_rows<T, S, 18, NT>(a, nk, R, pstride);
   if constexpr (N % 12 == 0) if (d == 12) return column_fft_rows<T, S, 12, NT>(a, nk, R, pstride);
   if constexpr (N % 10 == 0) if (d == 10) return column_fft_rows<T, S, 10, NT>(a, nk, R, pstride);
   if constexpr (N % 9 == 0) if (d == 9) return column_fft_rows<T, S, 9, NT>(a, nk, R, pstride);
@@ -239,6 +236,121 @@ __device__ __forceinline__ void forward_pruned(const Load& ld, int nf_active, in
       }
       __syncthreads();  // the next z pass overwrites the rows
     }
+  }
+}
+
+// Both fields of forward_pruned (NF = 2) side by side: two slab buffers
+// (fwd2_lds), so every pass works on the lines, rows and columns of both
+// fields at once.  For a slab of sx planes the z pass has 2 sx N lines, the
+// y pass 2 sx nk rows and the x stage 2 nk^2 columns, which fill a wide
+// workgroup better than one field at a time, with half the barriers.  Same
+// arithmetic, same order per field, as forward_pruned.
+template <class T>
+__host__ __device__ inline size_t fwd2_lds_bytes(int n, int nk, int sx) {
+  return sizeof(cplx<T>) * (2 * size_t(sx) * nk * slab_row(n) + n);
+}
+
+template <class T>
+__device__ inline SlabLds<T> fwd2_lds(void* base, int n, int nk, int sx) {
+  SlabLds<T> s;
+  s.t1 = reinterpret_cast<cplx<T>*>(base);
+  s.tw = s.t1 + 2 * size_t(sx) * nk * slab_row(n);
+  s.cmap = nullptr;
+  return s;
+}
+
+template <class T, int S, int D, int NT>
+__device__ inline void column_fft_rows2(cplx<T>* a, int nf, int nk, int R, int pstride,
+                                        int fstride) {
+  const int nc = nk * nk;
+  const unsigned inv = 0xffffffffu / unsigned(nk) + 1u;
+  for (int c = threadIdx.x; c < nf * nc; c += NT) {
+    const int f = c >= nc ? 1 : 0, cc = c - f * nc;
+    const int kzi = int(__umulhi(unsigned(cc), inv)), kyi = cc - kzi * nk;
+    cplx<T>* b = a + f * fstride + kzi * R + kyi;
+    cplx<T> v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = b[k * pstride];
+    Fft<T, S, D>::run(v);
+#pragma unroll
+    for (int k = 0; k < D; ++k) b[k * pstride] = v[k];
+  }
+}
+
+template <class T, int S, int N, int NT>
+__device__ inline void column_fft_rows2_tile(cplx<T>* a, int d, int nf, int nk, int R,
+                                             int pstride, int fstride) {
+  if constexpr (N % 12 == 0) if (d == 12) return column_fft_rows2<T, S, 12, NT>(a, nf, nk, R, pstride, fstride);
+  if constexpr (N % 10 == 0) if (d == 10) return column_fft_rows2<T, S, 10, NT>(a, nf, nk, R, pstride, fstride);
+  if constexpr (N % 9 == 0) if (d == 9) return column_fft_rows2<T, S, 9, NT>(a, nf, nk, R, pstride, fstride);
+  if constexpr (N % 8 == 0) if (d == 8) return column_fft_rows2<T, S, 8, NT>(a, nf, nk, R, pstride, fstride);
+  if constexpr (N % 6 == 0) if (d == 6) return column_fft_rows2<T, S, 6, NT>(a, nf, nk, R, pstride, fstride);
+  if constexpr (N % 5 == 0) if (d == 5) return column_fft_rows2<T, S, 5, NT>(a, nf, nk, R, pstride, fstride);
+  if constexpr (N % 4 == 0) if (d == 4) return column_fft_rows2<T, S, 4, NT>(a, nf, nk, R, pstride, fstride);
+  if constexpr (N % 3 == 0) if (d == 3) return column_fft_rows2<T, S, 3, NT>(a, nf, nk, R, pstride, fstride);
+  if constexpr (N % 2 == 0) if (d == 2) return column_fft_rows2<T, S, 2, NT>(a, nf, nk, R, pstride, fstride);
+}
+
+template <class T, int S, int N, int OPT, int NT = kThreads, int KM = -1, class Load>
+__device__ __forceinline__ void forward_pruned_joint(const Load& ld, int nf_active, int kmax_rt,
+                                                     int sx, const int (&gdesc)[OPT], int nout,
+                                                     cplx<T> (&acc)[2][OPT],
+                                                     const SlabLds<T>& L) {
+  constexpr int R = slab_row(N);
+  const int kmax = KM >= 0 ? KM : kmax_rt;
+  const int nk = 2 * kmax + 1, M = N / sx, pstride = nk * R, fstride = sx * pstride;
+  const int tid = threadIdx.x;
+  const int nl = sx * N, nr = sx * nk;
+  int ox[OPT];
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int kxm = gdesc[t] & 0xff, kyi = (gdesc[t] >> 8) & 0xff, kzi = gdesc[t] >> 16;
+    ox[t] = ((kxm % sx) * pstride + kzi * R + kyi) | (kxm << 24);
+  }
+  for (int x2 = 0; x2 < M; ++x2) {
+    // z pass: line (f, xs, y) -> rows (f, xs, kz)
+    for (int l = tid; l < nf_active * nl; l += NT) {
+      const int f = l >= nl ? 1 : 0, lf = l - f * nl;
+      const int xs = lf / N, y = lf - xs * N, x = x2 + M * xs;
+      cplx<T> v[N];
+#pragma unroll
+      for (int z = 0; z < N; ++z) v[z] = ld(f, x, y, z);
+      Fft<T, S, N>::run(v);
+      cplx<T>* out = L.t1 + f * fstride + xs * pstride + y;
+#pragma unroll
+      for (int z = 0; z < N; ++z) {
+        const int kz = (z <= N / 2) ? z : z - N;
+        if (kz >= -kmax && kz <= kmax) out[(kz + kmax) * R] = v[z];
+      }
+    }
+    __syncthreads();
+    // y pass: row (f, xs, kz) in place; the kept ky land at the row's start
+    for (int l = tid; l < nf_active * nr; l += NT) {
+      const int f = l >= nr ? 1 : 0;
+      cplx<T>* row = L.t1 + f * fstride + (l - f * nr) * R;
+      cplx<T> v[N];
+#pragma unroll
+      for (int y = 0; y < N; ++y) v[y] = row[y];
+      Fft<T, S, N>::run(v);
+#pragma unroll
+      for (int y = 0; y < N; ++y) {
+        const int ky = (y <= N / 2) ? y : y - N;
+        if (ky >= -kmax && ky <= kmax) row[ky + kmax] = v[y];
+      }
+    }
+    __syncthreads();
+    column_fft_rows2_tile<T, S, N, NT>(L.t1, sx, nf_active, nk, R, pstride, fstride);
+    if (sx > 1) __syncthreads();
+#pragma unroll
+    for (int t = 0; t < OPT; ++t) {
+      const int o = tid + t * NT;
+      if (o < nout) {
+        const cplx<T> tw = L.tw[((ox[t] >> 24) * x2) % N];
+        acc[0][t] = cfma(tw, L.t1[ox[t] & 0xffffff], acc[0][t]);
+        if (nf_active > 1) acc[1][t] = cfma(tw, L.t1[fstride + (ox[t] & 0xffffff)], acc[1][t]);
+      }
+    }
+    __syncthreads();  // the next z pass overwrites the rows
   }
 }
 
@@ -342,6 +454,49 @@ __device__ inline double block_sum(double v, double* red) {
     for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
   __syncthreads();
   return s;
+}
+
+// ---- partial sums by auxiliary cutoff shell ---------------------------------
+// Internal cutoff extrapolation: nested auxiliary spheres E_aux / alpha^(n-1),
+// n = 1..nb; shell[k] = the number of those spheres that contain auxiliary
+// vector k (1..nb).  A (G, G') term of a Coulomb-weighted sum belongs to the
+// energy of sphere n iff both vectors lie in it, so it is binned at
+// min(shell(G), shell(G')) - 1 and the energy of sphere n is the sum of bins
+// n-1 .. nb-1.
+constexpr int kMaxShells = 8;
+
+struct ShellBins {
+  const signed char* shell = nullptr;  // [n_g] (nullptr: no binning)
+  int nb = 0;                          // 1..kMaxShells
+  double* out = nullptr;               // [rows][nb] per-row bin sums
+};
+
+// Adds x into bin b (0 <= b < kMaxShells) without indexing a register array.
+__device__ __forceinline__ void bin_add(double (&sb)[kMaxShells], int b, double x) {
+#pragma unroll
+  for (int k = 0; k < kMaxShells; ++k) sb[k] += (k == b) ? x : 0.0;
+}
+
+// Block-wide sums of the kMaxShells bins (deterministic order), valid in
+// thread 0; red holds (blockDim.x / 64) * kMaxShells doubles.
+__device__ inline void block_sum_bins(double (&sb)[kMaxShells], double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kMaxShells; ++k) {
+    double v = sb[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[w * kMaxShells + k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kMaxShells; ++k) {
+      double s = 0.0;
+      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q * kMaxShells + k];
+      sb[k] = s;
+    }
+  }
+  __syncthreads();
 }
 
 }  // namespace ltmp2

@@ -28,7 +28,8 @@ EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_
             "ltmp2_mlp_last_error", "ltmp2_remez_polish", "ltmp2_batch_create",
             "ltmp2_batch_energy", "ltmp2_batch_info", "ltmp2_batch_group", "ltmp2_batch_cell",
             "ltmp2_batch_destroy", "ltmp2_batch_last_error", "ltmp2_batch_set_timing",
-            "ltmp2_batch_get_timing", "ltmp2_real_orbitals", "ltmp2_mlp_forward_noalloc")
+            "ltmp2_batch_get_timing", "ltmp2_real_orbitals", "ltmp2_mlp_forward_noalloc",
+            "ltmp2_get_extrapolation")
 MLP_NPARAM = 5976
 STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
 
@@ -38,7 +39,8 @@ class Params(C.Structure):
                 ("eaux", C.c_double), ("n_pw", C.c_int), ("n_states", C.c_int),
                 ("n_occ", C.c_int),
                 ("n_tau", C.c_int), ("quad_mode", C.c_int), ("prec", C.c_int),
-                ("workspace_cap", C.c_size_t)]
+                ("workspace_cap", C.c_size_t), ("n_extrap", C.c_int),
+                ("extrap_alpha", C.c_double)]
 
 
 class Info(C.Structure):
@@ -124,6 +126,7 @@ def load(path: str = LIB_PATH):
     lib.ltmp2_batch_last_error.restype = C.c_char_p
     lib.ltmp2_real_orbitals.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, vp, vp]
     lib.ltmp2_mlp_forward_noalloc.argtypes = [vp, vp, C.c_int, vp, vp]
+    lib.ltmp2_get_extrapolation.argtypes = [vp, vp, vp, vp, vp]
     lib.ltmp2_mlp_last_error.argtypes = []
     lib.ltmp2_mlp_last_error.restype = C.c_char_p
     for name in ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
@@ -134,7 +137,7 @@ def load(path: str = LIB_PATH):
                  "ltmp2_batch_create", "ltmp2_batch_energy", "ltmp2_batch_info",
                  "ltmp2_batch_group", "ltmp2_batch_cell", "ltmp2_batch_set_timing",
                  "ltmp2_batch_get_timing", "ltmp2_real_orbitals",
-                 "ltmp2_mlp_forward_noalloc"):
+                 "ltmp2_mlp_forward_noalloc", "ltmp2_get_extrapolation"):
         getattr(lib, name).restype = C.c_int
     lib.ltmp2_supported_grids.restype = C.c_int
     _lib = lib
@@ -307,7 +310,7 @@ class Context:
 
     def __init__(self, L, n_fft, ecut, eaux, miller, eps, coeff, n_occ, n_tau,
                  tau=None, w=None, prec=FP64, workspace_cap=0, stream=None,
-                 quad_mode=None, mlp_weights=None):
+                 quad_mode=None, mlp_weights=None, n_extrap=0, extrap_alpha=0.0):
         self.lib = load()
         miller = np.ascontiguousarray(miller, np.int32)
         eps = np.ascontiguousarray(eps, np.float64)
@@ -321,7 +324,8 @@ class Context:
         tau_a = None if tau is None else np.ascontiguousarray(tau, np.float64)
         w_a = None if w is None else np.ascontiguousarray(w, np.float64)
         p = Params(float(L), int(n_fft), float(ecut), float(eaux), int(miller.shape[0]),
-                   int(eps.shape[0]), int(n_occ), int(n_tau), int(quad_mode), int(prec), int(workspace_cap))
+                   int(eps.shape[0]), int(n_occ), int(n_tau), int(quad_mode), int(prec),
+                   int(workspace_cap), int(n_extrap), float(extrap_alpha))
         if stream is None:
             stream = _current_stream()
         self._ctx = C.c_void_p()
@@ -402,6 +406,14 @@ class Context:
         st = self.lib.ltmp2_exchange(self._ctx, itau, g_first, g_count, C.byref(e))
         _check(self.lib, st, self._ctx)
         return e.value
+
+    def extrapolation(self, n_extrap):
+        """After energy(): (e_aux [n], E_d [n], E_x [n], intercepts (E, E_d, E_x))."""
+        ea, ed, ex, ei = (np.zeros(n_extrap), np.zeros(n_extrap), np.zeros(n_extrap),
+                          np.zeros(3))
+        st = self.lib.ltmp2_get_extrapolation(self._ctx, _ptr(ea), _ptr(ed), _ptr(ex), _ptr(ei))
+        _check(self.lib, st, self._ctx)
+        return ea, ed, ex, ei
 
     def energy(self):
         """(E_d, E_x, per_tau [n_tau, 2], quad_err)."""

@@ -117,6 +117,9 @@ def test_validation_paths(lib, cell):
     _expect(lib, E, lambda: _setup(lib, s, m, e, c, tau=np.ones(8), w=None, quad_mode=2))
     _expect(lib, E, lambda: _setup(lib, s, m, e, c, tau=-np.ones(8), w=np.ones(8)))
     _expect(lib, E, lambda: _setup(lib, s, m, e, c, prec=7))
+    _expect(lib, E, lambda: _setup(lib, s, m, e, c, n_extrap=1))   # one cutoff: no fit
+    _expect(lib, E, lambda: _setup(lib, s, m, e, c, n_extrap=9))
+    _expect(lib, E, lambda: _setup(lib, s, m, e, c, n_extrap=8, extrap_alpha=0.9))
     _expect(lib, E, lambda: _setup(lib, s, m, e, c, quad_mode=9))
 
 

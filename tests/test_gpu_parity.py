@@ -407,3 +407,63 @@ def test_c2_subset16_vs_oracle(torch_cuda):
 def test_c3_subset16_vs_oracle(torch_cuda):
     from synthetic import C3
     _subset16("c3", C3)
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_c1_cutoff_extrapolation(c1_case, prec):
+    # internal cutoff extrapolation: the energies of the eight nested
+    # auxiliary cutoffs E_aux / 1.05^(n-1), taken from one pass of the path,
+    # against eight independent oracle evaluations with those auxiliary sets,
+    # and the intercepts of the E_aux^(-3/2) fit against the oracle's
+    from oracle.extrapolation import energies_at_cutoffs, extrapolate, cutoffs
+    m, e, c, P, tau, w, ref = c1_case
+    _say("C1 cutoff extrapolation, prec", prec)
+    ed_o, ex_o = energies_at_cutoffs(C1.L, C1.n, C1.eaux, m, e, c, C1.n_occ, tau, w)
+    with _ctx(C1, m, e, c, tau=tau, w=w, prec=prec, n_extrap=8) as ctx:
+        ed, ex, pt, qe = ctx.energy()
+        ea, edn, exn, einf = ctx.extrapolation(8)
+    assert np.allclose(ea, cutoffs(C1.eaux), rtol=1e-15)
+    assert abs(edn[0] - ed) <= 1e-12 * abs(ed) and abs(exn[0] - ex) <= 1e-12 * abs(ex)
+    ref_inf = [extrapolate(ea, ed_o + ex_o)[0], extrapolate(ea, ed_o)[0], extrapolate(ea, ex_o)[0]]
+    print(f"[extrap prec={prec}] max dE_d[n]={np.abs(edn - ed_o).max():.3e} "
+          f"max dE_x[n]={np.abs(exn - ex_o).max():.3e} E_inf={einf[0]:.10f} "
+          f"(oracle {ref_inf[0]:.10f})", flush=True)
+    if prec == 0:
+        assert np.allclose(edn, ed_o, rtol=1e-9, atol=0) and np.allclose(exn, ex_o, rtol=1e-9, atol=0)
+        assert np.allclose(einf, ref_inf, rtol=1e-8, atol=0)
+    else:
+        tol = C1.n_occ * 1e-6
+        assert np.abs(edn - ed_o).max() < tol and np.abs(exn - ex_o).max() < tol
+
+
+def test_c2_subset_cutoff_extrapolation(torch_cuda):
+    # the same on the 32^3 cell (two occupied orbitals, all virtuals) against
+    # stored oracle energies (tests/golden/make_extrapolation.py)
+    import json
+    import os
+    from synthetic import C2
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_extrapolation.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet")
+    ref = json.load(open(path))
+    m, e, c = make_cell(C2)
+    occ = np.array(ref["occ"])
+    sel = np.concatenate([occ, np.arange(C2.n_occ, len(e))])
+    sub = CellSpec(L=C2.L, n=C2.n, ecut=C2.ecut, eaux=C2.eaux, n_occ=len(occ), n_tau=C2.n_tau,
+                   seed=C2.seed)
+    for prec in (0, 2):
+        _say("C2 subset cutoff extrapolation, prec", prec)
+        with _ctx(sub, m, e[sel], c[sel], tau=np.array(ref["tau"]), w=np.array(ref["w"]),
+                  prec=prec, n_extrap=8) as ctx:
+            ctx.energy()
+            ea, edn, exn, einf = ctx.extrapolation(8)
+        dd = np.abs(edn - np.array(ref["e_d"])).max()
+        dx = np.abs(exn - np.array(ref["e_x"])).max()
+        print(f"[c2 extrap prec={prec}] max dE_d[n]={dd:.3e} max dE_x[n]={dx:.3e} "
+              f"E_inf={einf[0]:.10f} (oracle {ref['e_inf'][0]:.10f})", flush=True)
+        if prec == 0:
+            assert np.allclose(edn, ref["e_d"], rtol=1e-9, atol=0)
+            assert np.allclose(exn, ref["e_x"], rtol=1e-9, atol=0)
+            assert np.allclose(einf, ref["e_inf"], rtol=1e-8, atol=0)
+        else:
+            assert dd < len(occ) * 1e-6 and dx < len(occ) * 1e-6

@@ -237,3 +237,34 @@ def test_coulomb_kernel_absolute_normalisation(L, n):
     nd = cell.pair_densities(np.ones((1, n, n, n)), rg[None], aux)[0, 0]
     e_grid = 0.5 * float((v * np.abs(nd) ** 2).sum())
     assert abs(e_grid - e_cf) <= bound, (e_grid, e_cf)
+
+
+def test_extrapolation_line_fit_recovers_the_decay_law():
+    # y = a + b E^(-3/2) sampled at the cutoff array is fitted exactly; a
+    # noisy sample is fitted to within its noise (least squares)
+    from oracle.extrapolation import cutoffs, extrapolate
+    e = cutoffs(5.0)
+    assert np.allclose(e, [5.0 / 1.05 ** k for k in range(8)], rtol=1e-15)
+    a, b = extrapolate(e, -1.25 + 0.37 * e ** -1.5)
+    assert abs(a + 1.25) < 1e-13 and abs(b - 0.37) < 1e-12
+    rng = np.random.default_rng(4)
+    y = -1.25 + 0.37 * e ** -1.5 + rng.normal(0, 1e-9, e.size)
+    a, b = extrapolate(e, y)
+    X = np.stack([np.ones_like(e), e ** -1.5], 1)
+    ref = np.linalg.lstsq(X, y, rcond=None)[0]
+    assert abs(a - ref[0]) < 1e-12 and abs(b - ref[1]) < 1e-10
+
+
+def test_extrapolation_cutoff_energies_nested():
+    # the direct term sums non-negative contributions over nested auxiliary
+    # sets: E_d[n] is non-decreasing in n (less negative for smaller sets),
+    # and E[1] is the energy at the user-given cutoff
+    from oracle.extrapolation import energies_at_cutoffs
+    spec = tiny_spec(seed=2, L=6.0, n=10, ecut=3.0, eaux=3.0, n_occ=2)
+    m, e, c = make_cell(spec)
+    P = Problem(spec.L, spec.n, spec.eaux, m, e, c, spec.n_occ)
+    tau, w, _ = minimax_laplace(*P.x_range(), 6)
+    ed, ex = energies_at_cutoffs(spec.L, spec.n, spec.eaux, m, e, c, spec.n_occ, tau, w)
+    full = P.energies(tau, w)
+    assert abs(ed[0] - full["e_d_lt"]) < 1e-14 and abs(ex[0] - full["e_x_lt"]) < 1e-14
+    assert np.all(np.diff(ed) >= -1e-15) and ed[-1] > ed[0]
