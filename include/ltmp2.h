@@ -118,6 +118,8 @@ typedef struct {
   int g_block;           /* outer G' of the half set per transformed-state
                             block (the exchange runs ceil(n_h / g_block) blocks
                             per Laplace point; set by the workspace budget) */
+  int n_spin;            /* 1 (ltmp2_setup) or 2 (ltmp2_setup_unrestricted) */
+  int n_occ_b;           /* occupied states of the second spin channel        */
 } ltmp2_info;
 
 /*
@@ -142,6 +144,45 @@ typedef struct {
 ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller, const double* eps,
                          const double* coeff, const double* tau, const double* w,
                          const char* mlp_weights, void* hip_stream, ltmp2_ctx** out);
+
+/*
+ * Spin-unrestricted cell (Theory section, Eqs. MP2direct and MP2exchange):
+ * two spin channels with their own orbitals and energies on one basis.  The
+ * direct term sums over both channels of each of the two electron pairs, so
+ * it is evaluated once on chi = chi_up + chi_down (the products of the two
+ * channels' Green's functions added tile by tile); the exchange term couples
+ * one channel only and is evaluated per channel, each at half weight.  For
+ * identical channels every energy equals ltmp2_setup's.
+ *   p                    as ltmp2_setup; p->n_occ is channel 1's count
+ *   n_occ_b              occupied states of channel 2 (1 <= n_occ_b < n_states)
+ *   miller               one basis for both channels, as ltmp2_setup
+ *   eps_a, coeff_a       channel 1, laid out as ltmp2_setup's eps / coeff
+ *   eps_b, coeff_b       channel 2, same layout
+ *   tau, w, mlp_weights, hip_stream, out   as ltmp2_setup
+ * One Laplace quadrature serves both channels: it is fitted on
+ * [2 min(gap_1, gap_2), 2 max(spread_1, spread_2)] (gap: LUMO - HOMO,
+ * spread: highest - lowest state of a channel), so it covers every
+ * denominator of either channel; each channel keeps its own mu in its
+ * Green's functions (the Laplace factors do not depend on mu).
+ * On the returned context ltmp2_energy, ltmp2_chi, ltmp2_exchange and
+ * ltmp2_get_extrapolation return spin-summed values: per tau the direct value
+ * is 1/4 of the restricted trace formula on chi_up + chi_down (ltmp2_chi's
+ * chi_GG_dev is that sum's transform) and the exchange value half the sum of
+ * the two channels' restricted exchange values.  ltmp2_green returns channel
+ * 1's functions; ltmp2_direct_hartree answers LTMP2_ESTATE.  ltmp2_get_info
+ * reports n_spin = 2, n_occ_b and both channels' device bytes; ltmp2_destroy
+ * frees both.  Device memory: the overlap densities and orbitals of each
+ * channel; the chi and transformed-state scratch is shared (channel 2 runs
+ * its transformed-state blocks in channel 1's buffers, with as many outer G'
+ * per block as fit there, or in buffers of its own when not one fits).
+ * p->workspace_cap bounds each channel's footprint separately.
+ */
+ltmp2_status ltmp2_setup_unrestricted(const ltmp2_params* p, int n_occ_b, const int32_t* miller,
+                                      const double* eps_a, const double* coeff_a,
+                                      const double* eps_b, const double* coeff_b,
+                                      const double* tau, const double* w,
+                                      const char* mlp_weights, void* hip_stream,
+                                      ltmp2_ctx** out);
 
 /*
  * Occupied and virtual imaginary-time Green's functions at tau_itau
@@ -169,6 +210,20 @@ ltmp2_status ltmp2_green(ltmp2_ctx* ctx, int itau, int row0, int nrows, void* go
  * [n_g][n_g] in the library's auxiliary order (ltmp2_aux_miller).
  */
 ltmp2_status ltmp2_chi(ltmp2_ctx* ctx, int itau, void* chi_GG_dev, double* e_direct_tau);
+
+/*
+ * Direct term at tau_itau by the paper's own Hartree-like step (Implementation
+ * section, step (iv.a)): for every outer G', the transformed states
+ * w_i^{(G')} of the exchange path (Eqs. SCHnewstate, SCHtransmatrix), their
+ * sum h(r) = sum_i psi_i(r) w_i^{(G')}(r), its transform
+ * X(G) = dV sum_r e^{-iG.r} h(r) (= chi(G, -G') of the Green's-function
+ * route) and
+ *   *e_direct_tau = -2 sum_{G, G'} v(G) v(G') |X^{(G')}(G)|^2   (unweighted).
+ * Equal to ltmp2_chi's value; none of the Green's-function, chi-transform or
+ * trace kernels take part, so the two routes check each other.  Uses the
+ * context's chi scratch (LTMP2_ESTATE on a cell of a batch).
+ */
+ltmp2_status ltmp2_direct_hartree(ltmp2_ctx* ctx, int itau, double* e_direct_tau);
 
 /*
  * Exchange term at tau_itau through the transformed states of

@@ -29,6 +29,7 @@ struct ltmp2_ctx {
   long nrp = 0;  // padded row stride of grid arrays (multiple of 64)
   int kmax_aux = 0, kmax_orb = 0, gblock = 0;
   double omega = 0, dV = 0, mu = 0, xmin = 0, xmax = 0, quad_delta = 0;
+  double xmin_force = 0, xmax_force = 0;  // > 0: quadrature range of two spin channels
   int quad_flags = 0;
   std::string mlp_path;
   std::vector<double> eps, tau, w;
@@ -73,6 +74,9 @@ struct ltmp2_ctx {
   std::vector<double> ext_d, ext_x;  // [nb] energies per cutoff (last ltmp2_energy)
   double ext_inf[3] = {0, 0, 0};
 
+  // spin-unrestricted cells: the second spin channel (owned; shares the
+  // quadrature and the chi buffer of this context, which holds spin alpha)
+  ltmp2_ctx* beta = nullptr;
   std::vector<void*> owned;
   size_t bytes = 0;
 

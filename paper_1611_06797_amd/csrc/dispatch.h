@@ -41,6 +41,9 @@ struct GridOps {
   // all cells share the kept-set instance kfix (pair_kept)
   ltmp2_status (*pair_multi)(const PairCell* cells, const long* prefix, int ncells, int ng_max,
                              int kmax_max, int kfix, int sx, int nblocks, hipStream_t st);
+  // Hartree-like direct term of one block of outer G' from h (k_hartree)
+  ltmp2_status (*hartree)(const cplx<T>* h, long ld, const int* gdesc, int ng, const double* v,
+                          int kmax, double dV, int g0, int gb, double* pdh, hipStream_t st);
   int (*pair_sx_max)(int kmax);
   // kept-set instance of the pair kernels for a cell's kmax (or -1: runtime form)
   int (*pair_kept)(int kmax);
@@ -54,7 +57,8 @@ const GridOps<T>* grid_ops(int n);
 // upper-triangular tile pairs.
 template <int MODE>
 ltmp2_status launch_gf_chi(const void* psi, long ld, int no, int nv, const double* fo,
-                           const double* fv, void* chi, long ldc, long n, hipStream_t st);
+                           const double* fv, void* chi, long ldc, long n, int accumulate,
+                           hipStream_t st);
 template <int MODE>
 ltmp2_status launch_gemm_kmajor(const void* A, long lda, const void* B, long ldb, void* C,
                                 long ldc, int M, int N, int K, const double* sk,
@@ -67,10 +71,15 @@ ltmp2_status launch_split3(const float* src, long lds, int K, int Kpad, int M, l
                            const double* sk, int mode, void* hi, void* lo, long o0,
                            hipStream_t st);
 ltmp2_status launch_chi3(const void* hi, const void* lo, long ld, int kpo, int kpv, long n,
-                         float* chi, long ldc, hipStream_t st);
+                         float* chi, long ldc, int accumulate, hipStream_t st);
 ltmp2_status launch_mm3(const void* ahi, const void* alo, long lda, long am0, const void* bhi,
                         const void* blo, long ldb, float* C, long ldc, int M, int N, int Kpad,
                         const double* rowscale, int rdiv, int rmod, hipStream_t st);
+
+// h^{(G')}(r) = sum_i psi_i(r) w_i^{(G')}(r) for a block of gb outer vectors
+template <class T>
+ltmp2_status launch_hsum(const T* psi, long ld, const cplx<T>* w, int no, long nr, int gb,
+                         cplx<T>* h, hipStream_t st);
 
 // float -> double copy (diagnostic outputs of FP32 contexts)
 __global__ void k_widen(const float* in, double* out, long n);

@@ -156,6 +156,24 @@ ltmp2_status chi_cols(const cplx<T>* chihat, long ld, const int* gdesc, int ng, 
 }
 
 template <class T>
+struct HartreeF {
+  template <int OPT>
+  struct F {
+    static ltmp2_status go(const cplx<T>* h, long ld, const int* gdesc, int ng, const double* v,
+                           int kmax, double dV, int g0, int gb, double* pdh, hipStream_t st) {
+      const int nk = 2 * kmax + 1, sx = choose_sx_fwd<T>(nk);
+      return launch(k_hartree<T, N, OPT>, dim3(gb), fwd_lds_bytes<T>(N, nk, sx), st, h, ld, gdesc,
+                    ng, v, kmax, sx, dV, g0, pdh);
+    }
+  };
+};
+template <class T>
+ltmp2_status hartree(const cplx<T>* h, long ld, const int* gdesc, int ng, const double* v,
+                     int kmax, double dV, int g0, int gb, double* pdh, hipStream_t st) {
+  return by_opt<HartreeF<T>::template F>(ng, h, ld, gdesc, ng, v, kmax, dV, g0, gb, pdh, st);
+}
+
+template <class T>
 ltmp2_status wstates(const T* P, int npw, const int* wq, const signed char* wsgn, SphereCols sc,
                      int nitems, double scale, cplx<T>* w, long ld, hipStream_t st) {
   // the largest slab tile that lets four workgroups share a CU, unless two
@@ -337,7 +355,9 @@ int pair_sx_max(int kmax) {
                                 const signed char*, double*, int, int, hipStream_t);           \
   template ltmp2_status pair_multi<T>(const PairCell*, const long*, int, int, int, int, int,   \
                                       int, hipStream_t);                                       \
-  template int pair_sx_max<T>(int);
+  template int pair_sx_max<T>(int);                                                            \
+  template ltmp2_status hartree<T>(const cplx<T>*, long, const int*, int, const double*, int,   \
+                                   double, int, int, double*, hipStream_t);
 LTMP2_INST(double)
 LTMP2_INST(float)
 
@@ -350,10 +370,10 @@ extern const GridOps<double> LTMP2_CAT(kGridOpsD_, LTMP2_N);
 extern const GridOps<float> LTMP2_CAT(kGridOpsF_, LTMP2_N);
 const GridOps<double> LTMP2_CAT(kGridOpsD_, LTMP2_N) = {
     orbitals<double>, overlap<double>, chi_rows<double>, chi_cols<double>, wstates<double>,
-    pair<double>, pair_multi<double>, pair_sx_max<double>, pair_kept_instance};
+    pair<double>, pair_multi<double>, hartree<double>, pair_sx_max<double>, pair_kept_instance};
 const GridOps<float> LTMP2_CAT(kGridOpsF_, LTMP2_N) = {
     orbitals<float>, overlap<float>, chi_rows<float>, chi_cols<float>, wstates<float>,
-    pair<float>, pair_multi<float>, pair_sx_max<float>, pair_kept_instance};
+    pair<float>, pair_multi<float>, hartree<float>, pair_sx_max<float>, pair_kept_instance};
 #endif
 
 }  // namespace ltmp2

@@ -181,6 +181,68 @@ __global__ __launch_bounds__(kThreads) void k_chi_cols(const cplx<T>* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Hartree-like route to the direct term (Implementation section, step
+// (iv.a)), a cross-check of the chi route that shares none of its kernels:
+//   h^{(G')}(r)  = sum_i psi_i(r) w_i^{(G')}(r)
+//   X^{(G')}(G)  = dV sum_r e^{-iG.r} h^{(G')}(r)      (= chi(G, -G'))
+//   pdh[g0 + gl] = v(G') sum_G v(G) |X^{(G')}(G)|^2,   E_d(tau) = -4 sum_{H} pdh.
+// k_hsum: grid (ceil(n_r / 256), gb); h [gb][ld] complex.
+template <class T>
+__global__ __launch_bounds__(256) void k_hsum(const T* __restrict__ psi, long ld,
+                                              const cplx<T>* __restrict__ w, int no, long nr,
+                                              cplx<T>* __restrict__ h) {
+  const long r = long(blockIdx.x) * 256 + threadIdx.x;
+  const long gl = blockIdx.y;
+  if (r >= nr) return;
+  cplx<T> s = {T(0), T(0)};
+  for (int i = 0; i < no; ++i) {
+    const T a = psi[long(i) * ld + r];
+    const cplx<T> b = w[(gl * no + i) * ld + r];
+    s.x += a * b.x;
+    s.y += a * b.y;
+  }
+  h[gl * ld + r] = s;
+}
+
+// one block per outer vector gl of the block
+template <class T, int N, int OPT>
+__global__ __launch_bounds__(kThreads) void k_hartree(const cplx<T>* __restrict__ h, long ld,
+                                                      const int* __restrict__ gdesc_all, int ng,
+                                                      const double* __restrict__ v, int kmax,
+                                                      int sx, double dV, int g0,
+                                                      double* __restrict__ pdh) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double red[kThreads / 64];
+  const int nk = 2 * kmax + 1;
+  SlabLds<T> L = fwd_lds<T>(smem, N, nk, sx);
+  fill_twiddles<T, -1, N>(L.tw);
+  const int gl = blockIdx.x;
+  const cplx<T>* col = h + long(gl) * ld;
+  int gd[OPT];
+  cplx<T> acc[1][OPT];
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    gd[t] = (o < ng) ? gdesc_all[o] : 0;
+    acc[0][t] = {T(0), T(0)};
+  }
+  __syncthreads();
+  auto ld_ = [&](int, int x, int y, int z) { return col[(x * N + z) * N + y]; };
+  forward_pruned<T, -1, N, 1, OPT>(ld_, 1, kmax, sx, gd, ng, acc, L);
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < OPT; ++t) {
+    const int o = threadIdx.x + t * kThreads;
+    if (o < ng) {
+      const double re = dV * double(acc[0][t].x), im = dV * double(acc[0][t].y);
+      s += v[o] * (re * re + im * im);
+    }
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) pdh[g0 + gl] = v[g0 + gl] * s;
+}
+
+// ---------------------------------------------------------------------------
 // Transformed states on the grid (step (iii)):
 //   w_j^{(G')}(r) = Omega^-1/2 sum_G W_j(G) e^{iG.r},
 // with W_j(G) rebuilt from the real-basis product P = C Psi_v:

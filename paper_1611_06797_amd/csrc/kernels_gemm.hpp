@@ -1,6 +1,7 @@
 // Dense contractions of the LTMP2 path on CDNA matrix cores.
 //
 //   k_gf_chi:  chi(r, r') = G_occ(r, r') * G_vir(r, r') for one 64 x 64 tile
+//              (added to chi when accumulating the spin channels)
 //              pair (tile and its transpose; chi is symmetric for real
 //              orbitals), with
 //                G_occ = sum_i psi_i(r) exp((e_i - mu) tau) psi_i(r')
@@ -180,7 +181,8 @@ __global__ __launch_bounds__(256) void k_gf_chi(const typename Mma<MODE>::T* __r
                                                long ld, int no, int nv,
                                                const double* __restrict__ fo,
                                                const double* __restrict__ fv,
-                                               typename Mma<MODE>::T* __restrict__ chi, long ldc) {
+                                               typename Mma<MODE>::T* __restrict__ chi, long ldc,
+                                               int accumulate) {
   using T = typename Mma<MODE>::T;
   using Acc = typename Mma<MODE>::Acc;
   constexpr int BK = Mma<MODE>::BK;
@@ -214,8 +216,12 @@ __global__ __launch_bounds__(256) void k_gf_chi(const typename Mma<MODE>::T* __r
   __syncthreads();
   for (int e = tid; e < GB_M * GB_N; e += 256) {
     const int r = e >> 6, c = e & 63;
-    chi[(m0 + r) * ldc + n0 + c] = Cs[r][c];
-    if (bi != bj) chi[(n0 + r) * ldc + m0 + c] = Cs[c][r];
+    T* d = &chi[(m0 + r) * ldc + n0 + c];
+    *d = accumulate ? *d + Cs[r][c] : Cs[r][c];
+    if (bi != bj) {
+      T* dt = &chi[(n0 + r) * ldc + m0 + c];
+      *dt = accumulate ? *dt + Cs[c][r] : Cs[c][r];
+    }
   }
 }
 

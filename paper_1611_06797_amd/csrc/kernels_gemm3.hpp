@@ -155,14 +155,16 @@ __device__ __forceinline__ void m3_zero(f32x4 (&acc)[4][4]) {
     for (int q = 0; q < 4; ++q) acc[p][q] = f32x4{0.f, 0.f, 0.f, 0.f};
 }
 
-// chi(r, r') = G_occ(r, r') G_vir(r, r') from the split, sqrt-scaled orbitals
+// chi(r, r') = G_occ(r, r') G_vir(r, r') (added to chi when accumulating the
+// spin channels) from the split, sqrt-scaled orbitals
 // (occupied k-octets [0, kpo / 8), virtual ones [kpo / 8, (kpo + kpv) / 8)):
 // G_occ = sum_i (sqrt(f_i) psi_i)(r) (sqrt(f_i) psi_i)(r'), likewise G_vir.
 // Tiles are the upper-triangular pairs of an n x n block (t = n / 128 per
 // side) grouped in 8 x 8 super-tiles; the 64 workgroups of one super-tile run
 // on one XCD.  Off-diagonal tiles are also written transposed.
 __global__ __launch_bounds__(256, 2) void k_chi3(Op3 psi, int kpo, int kpv, int t,
-                                                float* __restrict__ chi, long ldc) {
+                                                float* __restrict__ chi, long ldc,
+                                                int accumulate) {
   __shared__ Split3Tile s[2];
   const int ts = (t + 7) / 8;
   const long nsuper = long(ts) * (ts + 1) / 2;
@@ -195,8 +197,12 @@ __global__ __launch_bounds__(256, 2) void k_chi3(Op3 psi, int kpo, int kpv, int 
       const f32x4 x = ao[p][q] * av[p][q];
       const long m = m0 + rb + 16 * p, n = n0 + cb + 16 * q;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) chi[(m + v) * ldc + n] = x[v];
-      if (bi != bj) *reinterpret_cast<f32x4*>(&chi[n * ldc + m]) = x;
+      for (int v = 0; v < 4; ++v)
+        chi[(m + v) * ldc + n] = accumulate ? chi[(m + v) * ldc + n] + x[v] : x[v];
+      if (bi != bj) {
+        f32x4* dt = reinterpret_cast<f32x4*>(&chi[n * ldc + m]);
+        *dt = accumulate ? *dt + x : x;
+      }
     }
 }
 

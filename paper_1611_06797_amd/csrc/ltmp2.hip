@@ -18,6 +18,13 @@
 
 using namespace ltmp2;
 
+// Spin sums of a two-channel (spin-unrestricted) cell, from the spin-orbital
+// energy (Theory section, "MP2 for periodic systems"): the direct term is
+// -1/2 sum_n w_n Tr[((chi_a + chi_b) v)^2], i.e. 1/4 of the spin-restricted
+// trace formula (-2 Tr[(chi v)^2]) applied to chi_a + chi_b; the exchange
+// term is 1/2 of the spin-restricted formula summed over the two channels.
+constexpr double kSpinDirect = 0.25, kSpinExchange = 0.5;
+
 namespace {
 
 thread_local std::string g_setup_error;
@@ -337,6 +344,10 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
   c->mu = 0.5 * (eps[c->no - 1] + eps[c->no]);
   c->xmin = 2.0 * (eps[c->no] - eps[c->no - 1]);
   c->xmax = 2.0 * (eps[c->nst - 1] - eps[0]);
+  if (c->xmax_force > 0.0) {
+    c->xmin = c->xmin_force;
+    c->xmax = c->xmax_force;
+  }
   c->npairs = c->no * (c->no + 1) / 2;
   if (c->npairs > (1 << 22) || c->no >= (1 << 15))
     return fail(nullptr, LTMP2_EINVAL, "too many occupied states");
@@ -534,7 +545,8 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
   c->esz = (P.prec == LTMP2_FP64) ? sizeof(double) : sizeof(float);
   const size_t es = c->esz;
   size_t fixed = es * (size_t(c->nst) * nrp + 2 * size_t(c->nv) * c->nh * c->no +
-                       size_t(c->nv) * c->ldbpw + nrp * nrp + 2 * size_t(c->nh) * nrp) +
+                       size_t(c->nv) * c->ldbpw +
+                       (c->own_scratch ? nrp * nrp + 2 * size_t(c->nh) * nrp : 0)) +
                  sizeof(double) * (size_t(c->nh) + size_t(c->nh) * c->npairs) +
                  sizeof(double) * 2 * size_t(c->nst) * c->npw;
   if (c->nb)
@@ -586,9 +598,6 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
       (c->own_scratch && (s = dalloc_bytes(c, &c->d_chi, es * nrp * nrp))) ||
       (c->own_scratch && (s = dalloc_bytes(c, &c->d_chihat, es * 2 * size_t(c->nh) * nrp))) ||
       (s = dalloc(c, &c->d_pd, c->nh)) ||
-      (c->own_scratch &&
-       (s = dalloc_bytes(c, &c->d_P, es * 2 * size_t(c->gblock) * c->no * c->npw))) ||
-      (c->own_scratch && (s = dalloc_bytes(c, &c->d_w, es * 2 * size_t(c->gblock) * c->no * nrp))) ||
       (s = dalloc(c, &c->d_xpart, size_t(c->nh) * c->npairs)) ||
       (s = dalloc(c, &c->d_xrow, size_t(c->nh))) ||
       (s = dalloc(c, &c->d_scal, 2 * size_t(c->ntau) + 8)))
@@ -613,6 +622,17 @@ ltmp2_status setup_impl(ltmp2_ctx* c, const int32_t* miller, const double* eps,
       return s;
     HIPCHK(c, hipMemsetAsync(c->d_scalb, 0, sizeof(double) * 2 * size_t(c->ntau) * c->nb,
                              c->stream));
+  }
+  // transformed-state buffers last, sized by what the cap leaves
+  if (c->own_scratch) {
+    if (P.workspace_cap) {
+      if (c->bytes + per_g > P.workspace_cap)
+        return fail(nullptr, LTMP2_ENOMEM, "device footprint exceeds the workspace cap");
+      c->gblock = (int)std::min<size_t>(c->gblock, (P.workspace_cap - c->bytes) / per_g);
+    }
+    if ((s = dalloc_bytes(c, &c->d_P, es * 2 * size_t(c->gblock) * c->no * c->npw)) ||
+        (s = dalloc_bytes(c, &c->d_w, es * 2 * size_t(c->gblock) * c->no * nrp)))
+      return s;
   }
   if (P.workspace_cap && c->bytes > P.workspace_cap)
     return fail(nullptr, LTMP2_ENOMEM, "device footprint exceeds the workspace cap");
@@ -640,29 +660,40 @@ ltmp2_status usable(ltmp2_ctx* c, int itau) {
   return LTMP2_OK;
 }
 
-// direct term at one Laplace point; value left in d_scal[2 * itau]
+// chi(r, r') = G_occ(r, r') G_vir(r', r) of context c's orbitals at tau_itau
+// into `chi` (added to it when accumulate is set: the second spin channel)
+template <class T, int MODE>
+ltmp2_status chi_tiles_t(ltmp2_ctx* c, int itau, void* chi, int accumulate) {
+  const double* fo = c->d_fo + size_t(itau) * c->no;
+  const double* fv = c->d_fv + size_t(itau) * c->nv;
+  ltmp2_status s;
+  if constexpr (MODE == kBF16x3) {
+    const float* psi = static_cast<const float*>(c->d_psi);
+    s = launch_split3(psi, c->nrp, c->no, c->kpo, int(c->nrp), c->nrp, fo, 2, c->d_psi3h,
+                      c->d_psi3l, 0, c->stream);
+    if (!s)
+      s = launch_split3(psi + long(c->no) * c->nrp, c->nrp, c->nv, c->kpv, int(c->nrp), c->nrp,
+                        fv, 2, c->d_psi3h, c->d_psi3l, c->kpo / 8, c->stream);
+    if (!s)
+      s = launch_chi3(c->d_psi3h, c->d_psi3l, c->nrp, c->kpo, c->kpv, c->nrp,
+                      static_cast<float*>(chi), c->nrp, accumulate, c->stream);
+  } else {
+    s = launch_gf_chi<MODE>(c->d_psi, c->nrp, c->no, c->nv, fo, fv, chi, c->nrp, c->nrp,
+                            accumulate, c->stream);
+  }
+  return s;
+}
+
+// direct term at one Laplace point; value left in d_scal[2 * itau].  With a
+// second spin channel (c->beta) chi is the sum of both channels' products.
 template <class T, int MODE>
 ltmp2_status run_direct_t(ltmp2_ctx* c, int itau, double* chi_out) {
   ltmp2_status s;
   const GridOps<T>* ops = grid_ops<T>(c->n);
-  const double* fo = c->d_fo + size_t(itau) * c->no;
-  const double* fv = c->d_fv + size_t(itau) * c->nv;
   {
     StageTimer tm(c, 0);
-    if constexpr (MODE == kBF16x3) {
-      const float* psi = static_cast<const float*>(c->d_psi);
-      s = launch_split3(psi, c->nrp, c->no, c->kpo, int(c->nrp), c->nrp, fo, 2, c->d_psi3h,
-                        c->d_psi3l, 0, c->stream);
-      if (!s)
-        s = launch_split3(psi + long(c->no) * c->nrp, c->nrp, c->nv, c->kpv, int(c->nrp), c->nrp,
-                          fv, 2, c->d_psi3h, c->d_psi3l, c->kpo / 8, c->stream);
-      if (!s)
-        s = launch_chi3(c->d_psi3h, c->d_psi3l, c->nrp, c->kpo, c->kpv, c->nrp,
-                        static_cast<float*>(c->d_chi), c->nrp, c->stream);
-    } else {
-      s = launch_gf_chi<MODE>(c->d_psi, c->nrp, c->no, c->nv, fo, fv, c->d_chi, c->nrp, c->nrp,
-                              c->stream);
-    }
+    s = chi_tiles_t<T, MODE>(c, itau, c->d_chi, 0);
+    if (!s && c->beta) s = chi_tiles_t<T, MODE>(c->beta, itau, c->d_chi, 1);
   }
   if (s) return fail(c, s, "chi tile launch failed");
   {
@@ -845,7 +876,49 @@ ltmp2_status green_split3(ltmp2_ctx* c, int itau, int row0, int nrows, double* g
   return LTMP2_OK;
 }
 
+// Direct term at one Laplace point through the transformed states (the
+// Hartree-like step (iv.a)): per block of outer G', the W GEMM and synthesis
+// of the exchange path, h = sum_i psi_i w_i, its transform onto the
+// auxiliary set and the Coulomb-weighted sum; value in d_scal[2 n_tau].
+template <class T>
+ltmp2_status hartree_tau_t(ltmp2_ctx* c, int itau) {
+  const GridOps<T>* ops = grid_ops<T>(c->n);
+  ltmp2_status s;
+  cplx<T>* h = static_cast<cplx<T>*>(c->d_chi);  // free outside the chi route
+  for (int g0 = 0; g0 < c->nh; g0 += c->gblock) {
+    const int gb = std::min(c->gblock, c->nh - g0);
+    if ((s = block_prepare(c, itau, g0, gb))) return s;
+    if ((s = launch_hsum<T>(static_cast<const T*>(c->d_psi), c->nrp,
+                            static_cast<const cplx<T>*>(c->d_w), c->no, c->nr, gb, h, c->stream)))
+      return fail(c, s, "state-sum launch failed");
+    if ((s = ops->hartree(h, c->nrp, c->d_gdesc, c->ng, c->d_v, c->kmax_aux, c->dV, g0, gb,
+                          c->d_pd, c->stream)))
+      return fail(c, s, "Hartree-like transform launch failed");
+  }
+  hipLaunchKernelGGL(k_reduce_direct, dim3(1), dim3(256), 0, c->stream, c->d_pd, c->nh,
+                     c->d_scal + 2 * c->ntau);
+  return check_launch(c, "k_reduce_direct");
+}
+
 }  // namespace
+
+extern "C" ltmp2_status ltmp2_direct_hartree(ltmp2_ctx* c, int itau, double* e_direct_tau) {
+  ltmp2_status s = usable(c, itau);
+  if (s) return s;
+  if (!c->own_scratch || !c->d_chi)
+    return fail(c, LTMP2_ESTATE, "the Hartree-like route needs a context of its own (ltmp2_setup)");
+  if (c->beta)
+    return fail(c, LTMP2_ESTATE, "the Hartree-like route covers spin-restricted cells");
+  s = (c->prm.prec == LTMP2_FP64) ? hartree_tau_t<double>(c, itau) : hartree_tau_t<float>(c, itau);
+  if (s) return s;
+  double v = 0.0;
+  HIPCHK(c, hipMemcpyAsync(&v, c->d_scal + 2 * c->ntau, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!std::isfinite(v)) return fail(c, LTMP2_ENUMERIC, "non-finite direct term");
+  if (e_direct_tau) *e_direct_tau = v;
+  return LTMP2_OK;
+}
 
 namespace ltmp2 {
 ltmp2_status run_direct(ltmp2_ctx* c, int itau, double* chi_out) {
@@ -896,6 +969,74 @@ extern "C" ltmp2_status ltmp2_setup(const ltmp2_params* p, const int32_t* miller
   return LTMP2_OK;
 }
 
+extern "C" ltmp2_status ltmp2_setup_unrestricted(const ltmp2_params* p, int n_occ_b,
+                                                 const int32_t* miller, const double* eps_a,
+                                                 const double* coeff_a, const double* eps_b,
+                                                 const double* coeff_b, const double* tau,
+                                                 const double* w, const char* mlp_weights,
+                                                 void* hip_stream, ltmp2_ctx** out) {
+  if (!out) return fail(nullptr, LTMP2_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(nullptr, LTMP2_EINVAL, "params is NULL");
+  ltmp2_params pb = *p;
+  pb.n_occ = n_occ_b;
+  std::vector<double> creal_a, creal_b;
+  ltmp2_status s = validate_and_realise(p, miller, eps_a, coeff_a, tau, w, creal_a, &coeff_a);
+  if (s) return s;
+  if ((s = validate_and_realise(&pb, miller, eps_b, coeff_b, tau, w, creal_b, &coeff_b)))
+    return fail(nullptr, s, "spin channel 2: " + g_setup_error);
+  // common quadrature range: every denominator of either channel
+  const int nst = p->n_states ? p->n_states : p->n_pw;
+  const double xmin = 2.0 * std::min(eps_a[p->n_occ] - eps_a[p->n_occ - 1],
+                                     eps_b[n_occ_b] - eps_b[n_occ_b - 1]);
+  const double xmax = 2.0 * std::max(eps_a[nst - 1] - eps_a[0], eps_b[nst - 1] - eps_b[0]);
+  ltmp2_ctx* c = new ltmp2_ctx();
+  c->prm = *p;
+  if (mlp_weights) c->mlp_path = mlp_weights;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->xmin_force = xmin;
+  c->xmax_force = xmax;
+  s = setup_impl(c, miller, eps_a, coeff_a, tau, w);
+  if (!s) {
+    // channel 2 takes channel 1's quadrature and shares its scratch
+    ltmp2_ctx* b = new ltmp2_ctx();
+    c->beta = b;
+    b->prm = pb;
+    b->prm.quad_mode = LTMP2_QUAD_GIVEN;
+    b->stream = c->stream;
+    b->own_scratch = false;
+    b->xmin_force = xmin;
+    b->xmax_force = xmax;
+    s = setup_impl(b, miller, eps_b, coeff_b, c->tau.data(), c->w.data());
+    if (s) {
+      if (!b->err.empty() && g_setup_error.empty()) g_setup_error = b->err;
+      g_setup_error = "spin channel 2: " + g_setup_error;
+    } else {
+      // transformed-state blocks of channel 2 in channel 1's P / w buffers
+      const long room = long(c->gblock) * c->no;
+      if (room >= b->no) {
+        b->gblock = int(std::min<long>(b->nh, room / b->no));
+        b->d_P = c->d_P;
+        b->d_w = c->d_w;
+      } else {
+        const size_t es = b->esz;
+        if ((s = dalloc_bytes(b, &b->d_P, es * 2 * size_t(b->gblock) * b->no * b->npw)) ||
+            (s = dalloc_bytes(b, &b->d_w, es * 2 * size_t(b->gblock) * b->no * b->nrp)))
+          g_setup_error = "spin channel 2: " + b->err;
+      }
+      b->d_chi = c->d_chi;  // chi tiles of channel 2 accumulate here
+      b->d_chihat = c->d_chihat;
+    }
+  }
+  if (s) {
+    if (!c->err.empty() && g_setup_error.empty()) g_setup_error = c->err;
+    ltmp2_destroy(c);
+    return s;
+  }
+  *out = c;
+  return LTMP2_OK;
+}
+
 extern "C" ltmp2_status ltmp2_green(ltmp2_ctx* c, int itau, int row0, int nrows, void* gocc,
                                     void* gvir) {
   ltmp2_status s = usable(c, itau);
@@ -925,7 +1066,7 @@ extern "C" ltmp2_status ltmp2_chi(ltmp2_ctx* c, int itau, void* chi_GG_dev, doub
   HIPCHK(c, hipMemcpyAsync(&v, c->d_scal + 2 * itau, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (!std::isfinite(v)) return fail(c, LTMP2_ENUMERIC, "non-finite direct term");
-  if (e_direct_tau) *e_direct_tau = v;
+  if (e_direct_tau) *e_direct_tau = c->beta ? kSpinDirect * v : v;
   return LTMP2_OK;
 }
 
@@ -939,10 +1080,16 @@ extern "C" ltmp2_status ltmp2_exchange(ltmp2_ctx* c, int itau, int g_first, int 
   }
   if (g_first < 0 || g_first + g_count > c->nh) return fail(c, LTMP2_EINVAL, "G' range outside H");
   if ((s = exchange_tau(c, itau, g_first, g_count))) return s;
-  double v = 0.0;
+  if (c->beta && (s = exchange_tau(c->beta, itau, g_first, g_count)))
+    return fail(c, s, "spin beta: " + c->beta->err);
+  double v = 0.0, vb = 0.0;
   HIPCHK(c, hipMemcpyAsync(&v, c->d_scal + 2 * itau + 1, sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
+  if (c->beta)
+    HIPCHK(c, hipMemcpyAsync(&vb, c->beta->d_scal + 2 * itau + 1, sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->beta) v = kSpinExchange * (v + vb);
   if (!std::isfinite(v)) return fail(c, LTMP2_ENUMERIC, "non-finite exchange term");
   if (e_exchange_tau) *e_exchange_tau = v;
   return LTMP2_OK;
@@ -969,10 +1116,22 @@ double line_intercept(const std::vector<double>& x, const std::vector<double>& y
 // n-1 .. nb-1) and their extrapolation in eaux^(-3/2) (Eq. CutDecay).
 static ltmp2_status assemble_extrapolation(ltmp2_ctx* c) {
   const int nb = c->nb;
-  std::vector<double> bins(2 * size_t(c->ntau) * nb);
+  std::vector<double> bins(2 * size_t(c->ntau) * nb), bb;
   HIPCHK(c, hipMemcpyAsync(bins.data(), c->d_scalb, sizeof(double) * bins.size(),
                            hipMemcpyDeviceToHost, c->stream));
+  if (c->beta) {
+    bb.resize(bins.size());
+    HIPCHK(c, hipMemcpyAsync(bb.data(), c->beta->d_scalb, sizeof(double) * bb.size(),
+                             hipMemcpyDeviceToHost, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->beta)
+    for (int t = 0; t < c->ntau; ++t)
+      for (int q = 0; q < nb; ++q) {
+        bins[(2 * size_t(t)) * nb + q] *= kSpinDirect;
+        double& x = bins[(2 * size_t(t) + 1) * nb + q];
+        x = kSpinExchange * (x + bb[(2 * size_t(t) + 1) * nb + q]);
+      }
   c->ext_d.assign(nb, 0.0);
   c->ext_x.assign(nb, 0.0);
   for (int t = 0; t < c->ntau; ++t)
@@ -1014,11 +1173,23 @@ extern "C" ltmp2_status ltmp2_energy(ltmp2_ctx* c, double* e_direct, double* e_e
   for (int t = 0; t < c->ntau; ++t) {
     if ((s = direct_tau(c, t, nullptr))) return s;
     if ((s = exchange_tau(c, t, 0, c->nh))) return s;
+    if (c->beta && (s = exchange_tau(c->beta, t, 0, c->nh)))
+      return fail(c, s, "spin beta: " + c->beta->err);
   }
-  std::vector<double> pt(2 * size_t(c->ntau));
+  std::vector<double> pt(2 * size_t(c->ntau)), pb;
   HIPCHK(c, hipMemcpyAsync(pt.data(), c->d_scal, sizeof(double) * pt.size(), hipMemcpyDeviceToHost,
                            c->stream));
+  if (c->beta) {
+    pb.resize(pt.size());
+    HIPCHK(c, hipMemcpyAsync(pb.data(), c->beta->d_scal, sizeof(double) * pb.size(),
+                             hipMemcpyDeviceToHost, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->beta)  // spin-summed per-tau values of the two channels
+    for (int t = 0; t < c->ntau; ++t) {
+      pt[2 * t] *= kSpinDirect;
+      pt[2 * t + 1] = kSpinExchange * (pt[2 * t + 1] + pb[2 * t + 1]);
+    }
   double ed = 0.0, ex = 0.0;
   for (int t = 0; t < c->ntau; ++t) {
     ed += c->w[t] * pt[2 * t];
@@ -1058,6 +1229,9 @@ extern "C" ltmp2_status ltmp2_get_info(const ltmp2_ctx* c, ltmp2_info* info) {
   info->quad_flags = c->quad_flags;
   info->n_grid = c->n;
   info->g_block = c->gblock;
+  info->n_spin = c->beta ? 2 : 1;
+  info->n_occ_b = c->beta ? c->beta->no : c->no;
+  if (c->beta) info->device_bytes += c->beta->bytes;
   return LTMP2_OK;
 }
 
@@ -1069,25 +1243,37 @@ extern "C" ltmp2_status ltmp2_aux_miller(const ltmp2_ctx* c, int32_t* out) {
 
 extern "C" ltmp2_status ltmp2_set_timing(ltmp2_ctx* c, int on) {
   if (!c) return LTMP2_EINVAL;
-  collect_timing(c);
-  c->timing = on != 0;
-  for (int k = 0; k < 8; ++k) {
-    c->stage_ms[k] = 0.0;
-    c->stage_n[k] = 0;
+  for (ltmp2_ctx* x = c; x; x = x->beta) {
+    collect_timing(x);
+    x->timing = on != 0;
+    for (int k = 0; k < 8; ++k) {
+      x->stage_ms[k] = 0.0;
+      x->stage_n[k] = 0;
+    }
   }
   return LTMP2_OK;
 }
 
 extern "C" ltmp2_status ltmp2_get_timing(ltmp2_ctx* c, int stage, double* ms, long* launches) {
   if (!c || stage < 0 || stage > 6) return LTMP2_EINVAL;
-  collect_timing(c);
-  if (ms) *ms = c->stage_ms[stage];
-  if (launches) *launches = c->stage_n[stage];
+  double t = 0.0;
+  long n = 0;
+  for (ltmp2_ctx* x = c; x; x = x->beta) {  // both spin channels
+    collect_timing(x);
+    t += x->stage_ms[stage];
+    n += x->stage_n[stage];
+  }
+  if (ms) *ms = t;
+  if (launches) *launches = n;
   return LTMP2_OK;
 }
 
 extern "C" void ltmp2_destroy(ltmp2_ctx* c) {
   if (!c) return;
+  if (c->beta) {
+    ltmp2_destroy(c->beta);
+    c->beta = nullptr;
+  }
   if (c->stream || !c->owned.empty()) (void)hipStreamSynchronize(c->stream);
   collect_timing(c);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);

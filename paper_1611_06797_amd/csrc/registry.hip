@@ -55,12 +55,14 @@ std::vector<int> supported_grids() {
 
 template <int MODE>
 ltmp2_status launch_gf_chi(const void* psi, long ld, int no, int nv, const double* fo,
-                           const double* fv, void* chi, long ldc, long n, hipStream_t st) {
+                           const double* fv, void* chi, long ldc, long n, int accumulate,
+                           hipStream_t st) {
   using T = typename Mma<MODE>::T;
   if (n % 64 != 0) return LTMP2_EINVAL;
   const long t = n / 64;
   hipLaunchKernelGGL(k_gf_chi<MODE>, dim3(unsigned(t * (t + 1) / 2)), dim3(256), 0, st,
-                     static_cast<const T*>(psi), ld, no, nv, fo, fv, static_cast<T*>(chi), ldc);
+                     static_cast<const T*>(psi), ld, no, nv, fo, fv, static_cast<T*>(chi), ldc,
+                     accumulate);
   return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
 }
 
@@ -89,13 +91,14 @@ ltmp2_status launch_split3(const float* src, long lds, int K, int Kpad, int M, l
 }
 
 ltmp2_status launch_chi3(const void* hi, const void* lo, long ld, int kpo, int kpv, long n,
-                         float* chi, long ldc, hipStream_t st) {
+                         float* chi, long ldc, int accumulate, hipStream_t st) {
   if (n % 128 != 0 || ld < n || kpo % 64 != 0 || kpv % 64 != 0) return LTMP2_EINVAL;
   const int t = int(n / 128), ts = (t + 7) / 8;
   const long nsuper = long(ts) * (ts + 1) / 2;
   const long blocks = (nsuper + 7) / 8 * 512;
   Op3 op{static_cast<const __bf16*>(hi), static_cast<const __bf16*>(lo), ld};
-  hipLaunchKernelGGL(k_chi3, dim3(unsigned(blocks)), dim3(256), 0, st, op, kpo, kpv, t, chi, ldc);
+  hipLaunchKernelGGL(k_chi3, dim3(unsigned(blocks)), dim3(256), 0, st, op, kpo, kpv, t, chi, ldc,
+                     accumulate);
   return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
 }
 
@@ -115,11 +118,11 @@ ltmp2_status launch_mm3(const void* ahi, const void* alo, long lda, long am0, co
 }
 
 template ltmp2_status launch_gf_chi<kF64>(const void*, long, int, int, const double*, const double*,
-                                          void*, long, long, hipStream_t);
+                                          void*, long, long, int, hipStream_t);
 template ltmp2_status launch_gf_chi<kF32>(const void*, long, int, int, const double*, const double*,
-                                          void*, long, long, hipStream_t);
+                                          void*, long, long, int, hipStream_t);
 template ltmp2_status launch_gf_chi<kBF16x3>(const void*, long, int, int, const double*,
-                                             const double*, void*, long, long, hipStream_t);
+                                          const double*, void*, long, long, int, hipStream_t);
 template ltmp2_status launch_gemm_kmajor<kF64>(const void*, long, const void*, long, void*, long,
                                                int, int, int, const double*, const double*, int,
                                                int, hipStream_t);
@@ -129,6 +132,19 @@ template ltmp2_status launch_gemm_kmajor<kF32>(const void*, long, const void*, l
 template ltmp2_status launch_gemm_kmajor<kBF16x3>(const void*, long, const void*, long, void*,
                                                   long, int, int, int, const double*,
                                                   const double*, int, int, hipStream_t);
+
+template <class T>
+ltmp2_status launch_hsum(const T* psi, long ld, const cplx<T>* w, int no, long nr, int gb,
+                         cplx<T>* h, hipStream_t st) {
+  if (gb <= 0) return LTMP2_OK;
+  hipLaunchKernelGGL(k_hsum<T>, dim3(unsigned((nr + 255) / 256), unsigned(gb)), dim3(256), 0, st,
+                     psi, ld, w, no, nr, h);
+  return hipGetLastError() == hipSuccess ? LTMP2_OK : LTMP2_EDEVICE;
+}
+template ltmp2_status launch_hsum<double>(const double*, long, const cplx<double>*, int, long,
+                                          int, cplx<double>*, hipStream_t);
+template ltmp2_status launch_hsum<float>(const float*, long, const cplx<float>*, int, long, int,
+                                         cplx<float>*, hipStream_t);
 
 __global__ void k_widen(const float* in, double* out, long n) {
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -29,7 +29,7 @@ EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_
             "ltmp2_batch_energy", "ltmp2_batch_info", "ltmp2_batch_group", "ltmp2_batch_cell",
             "ltmp2_batch_destroy", "ltmp2_batch_last_error", "ltmp2_batch_set_timing",
             "ltmp2_batch_get_timing", "ltmp2_real_orbitals", "ltmp2_mlp_forward_noalloc",
-            "ltmp2_get_extrapolation")
+            "ltmp2_get_extrapolation", "ltmp2_direct_hartree", "ltmp2_setup_unrestricted")
 MLP_NPARAM = 5976
 STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
 
@@ -48,7 +48,7 @@ class Info(C.Structure):
                 ("n_occ", C.c_int), ("n_vir", C.c_int), ("n_tau", C.c_int),
                 ("x_min", C.c_double), ("x_max", C.c_double), ("quad_delta", C.c_double),
                 ("device_bytes", C.c_size_t), ("quad_flags", C.c_int), ("n_grid", C.c_int),
-                ("g_block", C.c_int)]
+                ("g_block", C.c_int), ("n_spin", C.c_int), ("n_occ_b", C.c_int)]
 
 
 class BatchStats(C.Structure):
@@ -81,6 +81,8 @@ def load(path: str = LIB_PATH):
     lib.ltmp2_setup.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_char_p, C.c_void_p,
                                 C.POINTER(C.c_void_p)]
+    lib.ltmp2_setup_unrestricted.argtypes = [C.POINTER(Params), C.c_int] + [C.c_void_p] * 7 + [
+        C.c_char_p, C.c_void_p, C.POINTER(C.c_void_p)]
     lib.ltmp2_green.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
     lib.ltmp2_chi.argtypes = [C.c_void_p, C.c_int, C.c_void_p, dp]
     lib.ltmp2_exchange.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, dp]
@@ -127,6 +129,7 @@ def load(path: str = LIB_PATH):
     lib.ltmp2_real_orbitals.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, vp, vp]
     lib.ltmp2_mlp_forward_noalloc.argtypes = [vp, vp, C.c_int, vp, vp]
     lib.ltmp2_get_extrapolation.argtypes = [vp, vp, vp, vp, vp]
+    lib.ltmp2_direct_hartree.argtypes = [vp, C.c_int, dp]
     lib.ltmp2_mlp_last_error.argtypes = []
     lib.ltmp2_mlp_last_error.restype = C.c_char_p
     for name in ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_energy",
@@ -137,7 +140,8 @@ def load(path: str = LIB_PATH):
                  "ltmp2_batch_create", "ltmp2_batch_energy", "ltmp2_batch_info",
                  "ltmp2_batch_group", "ltmp2_batch_cell", "ltmp2_batch_set_timing",
                  "ltmp2_batch_get_timing", "ltmp2_real_orbitals",
-                 "ltmp2_mlp_forward_noalloc", "ltmp2_get_extrapolation"):
+                 "ltmp2_mlp_forward_noalloc", "ltmp2_get_extrapolation",
+                 "ltmp2_direct_hartree", "ltmp2_setup_unrestricted"):
         getattr(lib, name).restype = C.c_int
     lib.ltmp2_supported_grids.restype = C.c_int
     _lib = lib
@@ -306,11 +310,16 @@ def read_mlp_weights(path):
 
 
 class Context:
-    """One prepared cell (ltmp2_setup ... ltmp2_destroy)."""
+    """One prepared cell (ltmp2_setup ... ltmp2_destroy).
+
+    second_spin=(eps_b, coeff_b, n_occ_b) prepares a spin-unrestricted cell
+    (ltmp2_setup_unrestricted): eps / coeff / n_occ are then spin channel 1.
+    """
 
     def __init__(self, L, n_fft, ecut, eaux, miller, eps, coeff, n_occ, n_tau,
                  tau=None, w=None, prec=FP64, workspace_cap=0, stream=None,
-                 quad_mode=None, mlp_weights=None, n_extrap=0, extrap_alpha=0.0):
+                 quad_mode=None, mlp_weights=None, n_extrap=0, extrap_alpha=0.0,
+                 second_spin=None):
         self.lib = load()
         miller = np.ascontiguousarray(miller, np.int32)
         eps = np.ascontiguousarray(eps, np.float64)
@@ -323,15 +332,29 @@ class Context:
                 QUAD_LEARNED if mlp_weights else QUAD_PLAIN)
         tau_a = None if tau is None else np.ascontiguousarray(tau, np.float64)
         w_a = None if w is None else np.ascontiguousarray(w, np.float64)
+        for a in (tau_a, w_a):
+            if a is not None and a.shape != (int(n_tau),):
+                raise ValueError("tau and w need n_tau entries")
         p = Params(float(L), int(n_fft), float(ecut), float(eaux), int(miller.shape[0]),
                    int(eps.shape[0]), int(n_occ), int(n_tau), int(quad_mode), int(prec),
                    int(workspace_cap), int(n_extrap), float(extrap_alpha))
         if stream is None:
             stream = _current_stream()
         self._ctx = C.c_void_p()
-        st = self.lib.ltmp2_setup(C.byref(p), _ptr(miller), _ptr(eps), _ptr(coeff), _ptr(tau_a),
-                                  _ptr(w_a), mlp_weights.encode() if mlp_weights else None,
-                                  C.c_void_p(stream), C.byref(self._ctx))
+        mw = mlp_weights.encode() if mlp_weights else None
+        if second_spin is None:
+            st = self.lib.ltmp2_setup(C.byref(p), _ptr(miller), _ptr(eps), _ptr(coeff),
+                                      _ptr(tau_a), _ptr(w_a), mw, C.c_void_p(stream),
+                                      C.byref(self._ctx))
+        else:
+            eps_b, coeff_b, n_occ_b = second_spin
+            _, eps_b, coeff_b = _cell_arrays(miller, eps_b, coeff_b)
+            if eps_b.shape != eps.shape or coeff_b.shape != coeff.shape:
+                raise ValueError("both spin channels need the same states and basis")
+            st = self.lib.ltmp2_setup_unrestricted(
+                C.byref(p), int(n_occ_b), _ptr(miller), _ptr(eps), _ptr(coeff), _ptr(eps_b),
+                _ptr(coeff_b), _ptr(tau_a), _ptr(w_a), mw, C.c_void_p(stream),
+                C.byref(self._ctx))
         _check(self.lib, st)
         self.info = self.get_info()
 
@@ -397,6 +420,13 @@ class Context:
         """Unweighted E_d(tau); optional chi(G, G') into a complex128 tensor [n_g, n_g]."""
         e = C.c_double()
         st = self.lib.ltmp2_chi(self._ctx, itau, _dptr(chi_out), C.byref(e))
+        _check(self.lib, st, self._ctx)
+        return e.value
+
+    def direct_hartree(self, itau):
+        """Unweighted E_d(tau) by the Hartree-like route (transformed states)."""
+        e = C.c_double()
+        st = self.lib.ltmp2_direct_hartree(self._ctx, itau, C.byref(e))
         _check(self.lib, st, self._ctx)
         return e.value
 

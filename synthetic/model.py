@@ -214,6 +214,33 @@ def make_cell(spec: CellSpec):
     """
     miller = orbital_miller(spec.L, spec.n, spec.ecut)
     H = hamiltonian(miller, spec.L, spec.seed, spec.amp)
+    eps, coeff = _real_eigh(miller, H)
+    return miller, eps, coeff
+
+
+def make_cell_spin(spec: CellSpec, n_occ_b: int, split: float = 0.1, split_seed: int = 1000):
+    """Two spin channels of one cell (a spin-polarised stand-in).
+
+    Channel 1 sees H + dV, channel 2 sees H - dV, with dV a second seeded
+    potential of amplitude `split` (seed `split_seed`), the way an exchange
+    splitting separates the two channels of an open-shell mean field.
+    Channel 1 holds spec.n_occ electrons, channel 2 n_occ_b.  Returns
+    (miller, eps_1, coeff_1, eps_2, coeff_2), each channel as make_cell's.
+    """
+    miller = orbital_miller(spec.L, spec.n, spec.ecut)
+    H = hamiltonian(miller, spec.L, spec.seed, spec.amp)
+    dV = hamiltonian(miller, spec.L, split_seed, split)
+    kin = np.diag(np.diag(dV).copy())
+    dV = dV - kin  # potential part only
+    e1, c1 = _real_eigh(miller, H + dV)
+    e2, c2 = _real_eigh(miller, H - dV)
+    assert 1 <= n_occ_b < e2.shape[0]
+    return miller, e1, c1, e2, c2
+
+
+def _real_eigh(miller: np.ndarray, H: np.ndarray):
+    """Eigenpairs of a time-reversal-invariant H in the real basis, with
+    coefficients in the plane-wave basis (state-major)."""
     U = _real_basis_sparse(miller)
     Hr = np.asarray((U.conj().T @ (U.T @ H.T).T))
     if np.abs(Hr.imag).max() > 1e-10 * max(1.0, np.abs(Hr.real).max()):
@@ -225,7 +252,7 @@ def make_cell(spec: CellSpec):
     sgn = np.sign(R[piv, np.arange(R.shape[1])])
     R = R * sgn[None, :]
     coeff = (U @ R).T.copy()
-    return miller, eps.copy(), coeff
+    return eps.copy(), coeff
 
 
 def make_cell_complex(spec: CellSpec, phase_seed: int | None = None):

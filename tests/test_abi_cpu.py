@@ -123,6 +123,24 @@ def test_validation_paths(lib, cell):
     _expect(lib, E, lambda: _setup(lib, s, m, e, c, quad_mode=9))
 
 
+def test_unrestricted_validation_paths(lib, cell):
+    # the second spin channel is validated on the host like the first
+    s, (m, e, c) = cell
+    E, G = 1, 2
+    for nb in (0, len(e)):
+        msg = _expect(lib, E, lambda: _setup(lib, s, m, e, c, second_spin=(e, c, nb)))
+        assert "spin channel 2" in msg
+    _expect(lib, E, lambda: _setup(lib, s, m, e, c, second_spin=(e[::-1].copy(), c, 3)))
+    e2 = e.copy()
+    e2[2] = e2[1]
+    msg = _expect(lib, G, lambda: _setup(lib, s, m, e, c, second_spin=(e2, c, 2)))
+    assert "spin channel 2" in msg
+    _expect(lib, E, lambda: _setup(lib, s, m, e, c, second_spin=(e, c * 1.01, 3)))
+    _expect(lib, E, lambda: _setup(lib, s, m, e, c, n_occ=0, second_spin=(e, c, 3)))
+    with pytest.raises(ValueError):
+        _setup(lib, s, m, e, c, second_spin=(e[:-1], c[:-1], 3))
+
+
 def test_workspace_cap_enomem(lib, cell):
     s, (m, e, c) = cell
     _expect(lib, 3, lambda: _setup(lib, s, m, e, c, workspace_cap=1024))

@@ -467,3 +467,37 @@ def test_c2_subset_cutoff_extrapolation(torch_cuda):
             assert np.allclose(einf, ref["e_inf"], rtol=1e-8, atol=0)
         else:
             assert dd < len(occ) * 1e-6 and dx < len(occ) * 1e-6
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_c1_direct_term_two_routes(c1_case, prec):
+    # the direct term by the Hartree-like step (transformed states, h =
+    # sum_i psi_i w_i, its transform and Coulomb sum) against the
+    # Green's-function chi route and the oracle; the two routes share no kernel
+    m, e, c, P, tau, w, ref = c1_case
+    _say("C1 direct term, Hartree-like route, prec", prec)
+    with _ctx(C1, m, e, c, tau=tau, w=w, prec=prec) as ctx:
+        for it in (0, 4, C1.n_tau - 1):
+            eh = ctx.direct_hartree(it)
+            ec = ctx.chi(it)
+            r = ref["per_tau_d"][it]
+            print(f"[hartree prec={prec} tau {it}] route diff {abs(eh - ec) / abs(r):.3e} "
+                  f"vs oracle {abs(eh - r) / abs(r):.3e}", flush=True)
+            if prec == 0:
+                assert abs(eh - ec) <= 1e-11 * abs(r) and abs(eh - r) <= 1e-10 * abs(r)
+            else:
+                assert abs(eh - r) <= 1e-4 * abs(r)
+
+
+def test_c1_direct_term_two_routes_blocked(torch_cuda):
+    # the Hartree-like route with the outer G' loop cut into blocks
+    spec = CellSpec(L=8.0, n=12, ecut=6.0, eaux=4.0, n_occ=12, n_tau=6, seed=0)
+    m, e, c = make_cell(spec)
+    _say("Hartree-like route, several G' blocks")
+    with _ctx(spec, m, e, c) as ctx:
+        full = ctx.info.device_bytes
+    with _ctx(spec, m, e, c, workspace_cap=int(full * 0.6)) as ctx:
+        assert ctx.info.g_block < ctx.info.n_h
+        for it in (1, 5):
+            eh, ec = ctx.direct_hartree(it), ctx.chi(it)
+            assert abs(eh - ec) <= 1e-11 * abs(ec)
