@@ -120,6 +120,9 @@ typedef struct {
                             per Laplace point; set by the workspace budget) */
   int n_spin;            /* 1 (ltmp2_setup) or 2 (ltmp2_setup_unrestricted) */
   int n_occ_b;           /* occupied states of the second spin channel        */
+  int n_k;               /* k-point mesh points per axis (ltmp2_setup_kpoints;
+                            1 otherwise).  With n_k > 1 the sizes above are
+                            those of the Born-von Karman supercell. */
 } ltmp2_info;
 
 /*
@@ -183,6 +186,42 @@ ltmp2_status ltmp2_setup_unrestricted(const ltmp2_params* p, int n_occ_b, const 
                                       const double* tau, const double* w,
                                       const char* mlp_weights, void* hip_stream,
                                       ltmp2_ctx** out);
+
+/*
+ * k-point sampling (Theory section, "MP2 for periodic systems" and "LTMP2 in
+ * the plane wave basis"; Eqs. BlochOrbital, 2eIPLWV, OverlapDens): the
+ * Gamma-centred n_k^3 mesh k = (2 pi / L) kappa / n_k, kappa in
+ * {0..n_k-1}^3, mesh index t = (kappa_x n_k + kappa_y) n_k + kappa_z.  The
+ * Bloch states of the N = n_k^3 mesh points are, unchanged, the orbitals of
+ * the Born-von Karman supercell of side n_k L (supercell Miller index
+ * n_k m + kappa), whose Gamma-point MP2 energy is N times the energy per
+ * unit cell of the mesh: the supercell's Coulomb wavevectors are the G + q of
+ * Eq. 2eIPLWV, its auxiliary sphere the cutoff on |G + q|, and momentum
+ * conservation is the orthogonality of its plane waves.  The context is that
+ * supercell, prepared by the Gamma-point path; every energy it returns
+ * (ltmp2_energy, ltmp2_chi, ltmp2_exchange, ltmp2_get_extrapolation,
+ * ltmp2_direct_hartree) is per unit cell.  Cost grows as N^4 (the paper's
+ * momentum-conserving loops grow as N^3).
+ *   p          p->L, p->n_fft: the unit cell and its grid (the supercell uses
+ *              n_k n_fft); p->n_states: bands per k (the same at every k);
+ *              p->n_occ: occupied bands per k; p->n_pw: sum of n_pw_k
+ *   n_k        mesh points per axis, 1..6
+ *   n_pw_k     [N] basis size of each mesh point
+ *   miller     [sum n_pw_k][3] int32, mesh point after mesh point: the m of
+ *              the plane waves e^{i (G + k).r}, G = (2 pi / L) m
+ *   eps        [N][n_states] band energies, ascending at each k
+ *   coeff      per mesh point [n_states][n_pw_k][2] (re, im), concatenated;
+ *              unit norm, time-reversal related (phi*_{k} = phi_{-k})
+ * Errors: LTMP2_EINVAL for inconsistent sizes or a supercell basis the
+ * Gamma-point rules reject (the per-k spheres of a cutoff make a supercell
+ * sphere); LTMP2_EGAP when an occupied band at one k lies above a virtual
+ * band at another (no common gap).  Host memory: the unfolded coefficient
+ * table, N n_states x n_pw doubles x 2, during setup.
+ */
+ltmp2_status ltmp2_setup_kpoints(const ltmp2_params* p, int n_k, const int32_t* n_pw_k,
+                                 const int32_t* miller, const double* eps, const double* coeff,
+                                 const double* tau, const double* w, const char* mlp_weights,
+                                 void* hip_stream, ltmp2_ctx** out);
 
 /*
  * Occupied and virtual imaginary-time Green's functions at tau_itau

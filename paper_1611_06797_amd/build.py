@@ -47,6 +47,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
              ("ltmp2.hip", "ltmp2.o", []),
              ("quadrature.cpp", "quadrature.o", ["-x", "hip"]),
              ("real_orbitals.cpp", "real_orbitals.o", ["-x", "hip"]),
+             ("kpoints.cpp", "kpoints.o", ["-x", "hip"]),
              ("mlp.hip", "mlp.o", []),
              ("batch.hip", "batch.o", [])]
     units += [("grid_kernels.hip", f"grid_{n}.o", [f"-DLTMP2_N={n}"]) for n in GRIDS]

@@ -30,6 +30,8 @@ struct ltmp2_ctx {
   int kmax_aux = 0, kmax_orb = 0, gblock = 0;
   double omega = 0, dV = 0, mu = 0, xmin = 0, xmax = 0, quad_delta = 0;
   double xmin_force = 0, xmax_force = 0;  // > 0: quadrature range of two spin channels
+  double escale = 1.0;  // energies per unit cell: 1 / N for the supercell of an N-point mesh
+  int n_kmesh = 1;      // k-point mesh points per axis (1: Gamma only)
   int quad_flags = 0;
   std::string mlp_path;
   std::vector<double> eps, tau, w;
@@ -110,6 +112,10 @@ const std::string& setup_error();
 void set_setup_error(const std::string& msg);
 // Orbitals real up to a phase (or degenerate blocks with a real basis) to
 // real form (real_orbitals.cpp); `out` stays empty if nothing changes.
+ltmp2_status unfold_kmesh(int n_k, int n_bands, int n_occ, const int32_t* n_pw_k,
+                          const int32_t* miller, const double* eps, const double* coeff,
+                          std::vector<int32_t>& miller_s, std::vector<double>& eps_s,
+                          std::vector<double>& coeff_s, std::string& err);
 ltmp2_status real_orbitals(int npw, const int32_t* miller, int nst, const double* eps, int nocc,
                            const double* coeff, std::vector<double>& out, bool* changed,
                            std::string& err);

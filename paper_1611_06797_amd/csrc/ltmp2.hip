@@ -916,7 +916,7 @@ extern "C" ltmp2_status ltmp2_direct_hartree(ltmp2_ctx* c, int itau, double* e_d
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (!std::isfinite(v)) return fail(c, LTMP2_ENUMERIC, "non-finite direct term");
-  if (e_direct_tau) *e_direct_tau = v;
+  if (e_direct_tau) *e_direct_tau = c->escale * v;
   return LTMP2_OK;
 }
 
@@ -1037,6 +1037,58 @@ extern "C" ltmp2_status ltmp2_setup_unrestricted(const ltmp2_params* p, int n_oc
   return LTMP2_OK;
 }
 
+extern "C" ltmp2_status ltmp2_setup_kpoints(const ltmp2_params* p, int n_k,
+                                            const int32_t* n_pw_k, const int32_t* miller,
+                                            const double* eps, const double* coeff,
+                                            const double* tau, const double* w,
+                                            const char* mlp_weights, void* hip_stream,
+                                            ltmp2_ctx** out) {
+  if (!out) return fail(nullptr, LTMP2_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p || !n_pw_k || !miller || !eps || !coeff)
+    return fail(nullptr, LTMP2_EINVAL, "NULL argument");
+  if (n_k < 1 || n_k > 6) return fail(nullptr, LTMP2_EINVAL, "n_k must be in [1, 6]");
+  const int nk = n_k * n_k * n_k;
+  long total = 0;
+  for (int t = 0; t < nk; ++t) total += n_pw_k[t];
+  if (total != p->n_pw)
+    return fail(nullptr, LTMP2_EINVAL, "n_pw must be the sum of the per-k basis sizes");
+  if (p->n_states <= 0) return fail(nullptr, LTMP2_EINVAL, "n_states (bands per k) must be set");
+  if (!(p->L > 0.0) || p->n_fft <= 0 || p->n_fft * n_k > 4096)
+    return fail(nullptr, LTMP2_EINVAL, "bad cell or grid");
+  std::vector<int32_t> ms;
+  std::vector<double> es, cs;
+  std::string err;
+  ltmp2_status s = unfold_kmesh(n_k, p->n_states, p->n_occ, n_pw_k, miller, eps, coeff, ms, es,
+                                cs, err);
+  if (s) return fail(nullptr, s, err);
+  // the Born-von Karman supercell as a Gamma-point cell
+  ltmp2_params ps = *p;
+  ps.L = p->L * n_k;
+  ps.n_fft = p->n_fft * n_k;
+  ps.n_pw = int(total);
+  ps.n_states = nk * p->n_states;
+  ps.n_occ = nk * p->n_occ;
+  const double* cuse = cs.data();
+  std::vector<double> creal;
+  if ((s = validate_and_realise(&ps, ms.data(), es.data(), cs.data(), tau, w, creal, &cuse)))
+    return fail(nullptr, s, "supercell of the mesh: " + g_setup_error);
+  ltmp2_ctx* c = new ltmp2_ctx();
+  c->prm = ps;
+  c->escale = 1.0 / nk;
+  c->n_kmesh = n_k;
+  if (mlp_weights) c->mlp_path = mlp_weights;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  s = setup_impl(c, ms.data(), es.data(), cuse, tau, w);
+  if (s) {
+    if (!c->err.empty() && g_setup_error.empty()) g_setup_error = c->err;
+    ltmp2_destroy(c);
+    return s;
+  }
+  *out = c;
+  return LTMP2_OK;
+}
+
 extern "C" ltmp2_status ltmp2_green(ltmp2_ctx* c, int itau, int row0, int nrows, void* gocc,
                                     void* gvir) {
   ltmp2_status s = usable(c, itau);
@@ -1066,7 +1118,7 @@ extern "C" ltmp2_status ltmp2_chi(ltmp2_ctx* c, int itau, void* chi_GG_dev, doub
   HIPCHK(c, hipMemcpyAsync(&v, c->d_scal + 2 * itau, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (!std::isfinite(v)) return fail(c, LTMP2_ENUMERIC, "non-finite direct term");
-  if (e_direct_tau) *e_direct_tau = c->beta ? kSpinDirect * v : v;
+  if (e_direct_tau) *e_direct_tau = c->escale * (c->beta ? kSpinDirect * v : v);
   return LTMP2_OK;
 }
 
@@ -1091,7 +1143,7 @@ extern "C" ltmp2_status ltmp2_exchange(ltmp2_ctx* c, int itau, int g_first, int 
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->beta) v = kSpinExchange * (v + vb);
   if (!std::isfinite(v)) return fail(c, LTMP2_ENUMERIC, "non-finite exchange term");
-  if (e_exchange_tau) *e_exchange_tau = v;
+  if (e_exchange_tau) *e_exchange_tau = c->escale * v;
   return LTMP2_OK;
 }
 
@@ -1132,6 +1184,7 @@ static ltmp2_status assemble_extrapolation(ltmp2_ctx* c) {
         double& x = bins[(2 * size_t(t) + 1) * nb + q];
         x = kSpinExchange * (x + bb[(2 * size_t(t) + 1) * nb + q]);
       }
+  for (double& x : bins) x *= c->escale;
   c->ext_d.assign(nb, 0.0);
   c->ext_x.assign(nb, 0.0);
   for (int t = 0; t < c->ntau; ++t)
@@ -1190,6 +1243,7 @@ extern "C" ltmp2_status ltmp2_energy(ltmp2_ctx* c, double* e_direct, double* e_e
       pt[2 * t] *= kSpinDirect;
       pt[2 * t + 1] = kSpinExchange * (pt[2 * t + 1] + pb[2 * t + 1]);
     }
+  for (double& x : pt) x *= c->escale;  // per unit cell of a k-point mesh
   double ed = 0.0, ex = 0.0;
   for (int t = 0; t < c->ntau; ++t) {
     ed += c->w[t] * pt[2 * t];
@@ -1230,6 +1284,7 @@ extern "C" ltmp2_status ltmp2_get_info(const ltmp2_ctx* c, ltmp2_info* info) {
   info->n_grid = c->n;
   info->g_block = c->gblock;
   info->n_spin = c->beta ? 2 : 1;
+  info->n_k = c->n_kmesh;
   info->n_occ_b = c->beta ? c->beta->no : c->no;
   if (c->beta) info->device_bytes += c->beta->bytes;
   return LTMP2_OK;

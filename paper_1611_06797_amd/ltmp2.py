@@ -29,7 +29,8 @@ EXPORTED = ("ltmp2_setup", "ltmp2_green", "ltmp2_chi", "ltmp2_exchange", "ltmp2_
             "ltmp2_batch_energy", "ltmp2_batch_info", "ltmp2_batch_group", "ltmp2_batch_cell",
             "ltmp2_batch_destroy", "ltmp2_batch_last_error", "ltmp2_batch_set_timing",
             "ltmp2_batch_get_timing", "ltmp2_real_orbitals", "ltmp2_mlp_forward_noalloc",
-            "ltmp2_get_extrapolation", "ltmp2_direct_hartree", "ltmp2_setup_unrestricted")
+            "ltmp2_get_extrapolation", "ltmp2_direct_hartree", "ltmp2_setup_unrestricted",
+            "ltmp2_setup_kpoints")
 MLP_NPARAM = 5976
 STAGES = ("chi_tiles", "chi_rows", "chi_cols", "w_gemm", "w_synth", "pair", "reduce")
 
@@ -48,7 +49,8 @@ class Info(C.Structure):
                 ("n_occ", C.c_int), ("n_vir", C.c_int), ("n_tau", C.c_int),
                 ("x_min", C.c_double), ("x_max", C.c_double), ("quad_delta", C.c_double),
                 ("device_bytes", C.c_size_t), ("quad_flags", C.c_int), ("n_grid", C.c_int),
-                ("g_block", C.c_int), ("n_spin", C.c_int), ("n_occ_b", C.c_int)]
+                ("g_block", C.c_int), ("n_spin", C.c_int), ("n_occ_b", C.c_int),
+                ("n_k", C.c_int)]
 
 
 class BatchStats(C.Structure):
@@ -82,6 +84,8 @@ def load(path: str = LIB_PATH):
                                 C.c_void_p, C.c_void_p, C.c_char_p, C.c_void_p,
                                 C.POINTER(C.c_void_p)]
     lib.ltmp2_setup_unrestricted.argtypes = [C.POINTER(Params), C.c_int] + [C.c_void_p] * 7 + [
+        C.c_char_p, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.ltmp2_setup_kpoints.argtypes = [C.POINTER(Params), C.c_int] + [C.c_void_p] * 6 + [
         C.c_char_p, C.c_void_p, C.POINTER(C.c_void_p)]
     lib.ltmp2_green.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
     lib.ltmp2_chi.argtypes = [C.c_void_p, C.c_int, C.c_void_p, dp]
@@ -141,7 +145,7 @@ def load(path: str = LIB_PATH):
                  "ltmp2_batch_group", "ltmp2_batch_cell", "ltmp2_batch_set_timing",
                  "ltmp2_batch_get_timing", "ltmp2_real_orbitals",
                  "ltmp2_mlp_forward_noalloc", "ltmp2_get_extrapolation",
-                 "ltmp2_direct_hartree", "ltmp2_setup_unrestricted"):
+                 "ltmp2_direct_hartree", "ltmp2_setup_unrestricted", "ltmp2_setup_kpoints"):
         getattr(lib, name).restype = C.c_int
     lib.ltmp2_supported_grids.restype = C.c_int
     _lib = lib
@@ -314,13 +318,32 @@ class Context:
 
     second_spin=(eps_b, coeff_b, n_occ_b) prepares a spin-unrestricted cell
     (ltmp2_setup_unrestricted): eps / coeff / n_occ are then spin channel 1.
+
+    kmesh=n_k prepares the n_k^3 k-point mesh of a cell (ltmp2_setup_kpoints):
+    miller and coeff are then lists over the mesh points (per-k Miller
+    indices [n_pw_k, 3], complex coefficients [bands, n_pw_k]), eps is
+    [n_k^3, bands], n_occ counts bands per k, and energies are per unit cell.
     """
 
     def __init__(self, L, n_fft, ecut, eaux, miller, eps, coeff, n_occ, n_tau,
                  tau=None, w=None, prec=FP64, workspace_cap=0, stream=None,
                  quad_mode=None, mlp_weights=None, n_extrap=0, extrap_alpha=0.0,
-                 second_spin=None):
+                 second_spin=None, kmesh=None):
         self.lib = load()
+        n_pw_k = None
+        if kmesh is not None:
+            if second_spin is not None:
+                raise ValueError("k-point meshes are spin-restricted")
+            n_pw_k = np.ascontiguousarray([len(m) for m in miller], np.int32)
+            eps = np.asarray(eps, np.float64)
+            if eps.ndim != 2 or eps.shape[0] != len(miller) or len(coeff) != len(miller):
+                raise ValueError("kmesh: one Miller set, energy row and coefficient block per k")
+            nb = eps.shape[1]
+            if any(np.asarray(cb).shape[:2] != (nb, len(m)) for cb, m in zip(coeff, miller)):
+                raise ValueError("kmesh: coefficients [bands, n_pw_k] per k")
+            miller = np.concatenate([np.asarray(m, np.int32) for m in miller])
+            coeff = np.concatenate([np.asarray(cb).reshape(-1, *np.asarray(cb).shape[2:])
+                                    for cb in coeff])
         miller = np.ascontiguousarray(miller, np.int32)
         eps = np.ascontiguousarray(eps, np.float64)
         coeff = np.asarray(coeff)
@@ -335,14 +358,19 @@ class Context:
         for a in (tau_a, w_a):
             if a is not None and a.shape != (int(n_tau),):
                 raise ValueError("tau and w need n_tau entries")
+        n_states = eps.shape[-1] if kmesh is not None else eps.shape[0]
         p = Params(float(L), int(n_fft), float(ecut), float(eaux), int(miller.shape[0]),
-                   int(eps.shape[0]), int(n_occ), int(n_tau), int(quad_mode), int(prec),
+                   int(n_states), int(n_occ), int(n_tau), int(quad_mode), int(prec),
                    int(workspace_cap), int(n_extrap), float(extrap_alpha))
         if stream is None:
             stream = _current_stream()
         self._ctx = C.c_void_p()
         mw = mlp_weights.encode() if mlp_weights else None
-        if second_spin is None:
+        if kmesh is not None:
+            st = self.lib.ltmp2_setup_kpoints(C.byref(p), int(kmesh), _ptr(n_pw_k), _ptr(miller),
+                                              _ptr(eps), _ptr(coeff), _ptr(tau_a), _ptr(w_a), mw,
+                                              C.c_void_p(stream), C.byref(self._ctx))
+        elif second_spin is None:
             st = self.lib.ltmp2_setup(C.byref(p), _ptr(miller), _ptr(eps), _ptr(coeff),
                                       _ptr(tau_a), _ptr(w_a), mw, C.c_void_p(stream),
                                       C.byref(self._ctx))

@@ -255,6 +255,73 @@ def _real_eigh(miller: np.ndarray, H: np.ndarray):
     return eps.copy(), coeff
 
 
+def kmesh_points(n_k: int) -> np.ndarray:
+    """Integer labels kappa of the Gamma-centred n_k^3 mesh, k = b kappa / n_k,
+    in the order kappa_x-major (index (kx n_k + ky) n_k + kz)."""
+    r = np.arange(n_k)
+    kx, ky, kz = np.meshgrid(r, r, r, indexing="ij")
+    return np.stack([kx.ravel(), ky.ravel(), kz.ravel()], axis=1)
+
+
+def kpoint_miller(L: float, n: int, ecut: float, kappa, n_k: int) -> np.ndarray:
+    """Miller indices m of the sphere |b (m + kappa / n_k)|^2 / 2 < ecut
+    (plane waves e^{i (G + k).r}), sorted lexicographically."""
+    b = 2.0 * math.pi / L
+    f = np.asarray(kappa, float) / n_k
+    mmax = int(math.floor(math.sqrt(2.0 * ecut) / b)) + 2
+    r = np.arange(-mmax, mmax + 1)
+    mx, my, mz = np.meshgrid(r, r, r, indexing="ij")
+    m = np.stack([mx.ravel(), my.ravel(), mz.ravel()], axis=1)
+    q = m + f[None, :]
+    keep = 0.5 * b * b * (q * q).sum(axis=1) < ecut * (1.0 - 1e-12)
+    m = m[keep]
+    if np.any(2 * np.abs(m) >= n):
+        raise ValueError("orbital sphere does not fit inside the FFT grid")
+    order = np.lexsort((m[:, 2], m[:, 1], m[:, 0]))
+    return np.ascontiguousarray(m[order].astype(np.int32))
+
+
+def make_cell_kmesh(spec: CellSpec, n_k: int, n_bands: int | None = None):
+    """Bloch states of one cell on the Gamma-centred n_k^3 mesh.
+
+    The cell and potential are spec's; at each k the Hamiltonian
+    H_k = |G + k|^2 / 2 delta + V(G - G') is diagonalised in the sphere of
+    kpoint_miller.  Time reversal is exact: for the mesh point k' = -k (mod
+    the mesh) the states are the complex conjugates, c_{k'}(m') =
+    conj(c_k(-m' - g0)) with k' + k = b g0.  Returns (kappas [N_k, 3],
+    millers [N_k] int32 arrays, eps [N_k, n_bands], coeffs [N_k] complex
+    arrays [n_bands, n_pw_k]); n_bands defaults to the smallest basis.
+    """
+    kap = kmesh_points(n_k)
+    b = 2.0 * math.pi / spec.L
+    mills = [kpoint_miller(spec.L, spec.n, spec.ecut, k, n_k) for k in kap]
+    nb = min(m.shape[0] for m in mills) if n_bands is None else int(n_bands)
+    allm = np.concatenate(mills)
+    V, M = potential_box(allm, spec.L, spec.seed, spec.amp)
+    index = {tuple(k): t for t, k in enumerate(kap.tolist())}
+    eps = np.zeros((len(kap), nb))
+    coeffs = [None] * len(kap)
+    for t, k in enumerate(kap):
+        kp = tuple(int(x) for x in (-k) % n_k)
+        tp = index[kp]
+        if tp < t:  # time-reversal partner done: conjugate its states
+            g0 = (np.asarray(kp) + k) // n_k
+            pos = {tuple(v): c for c, v in enumerate(mills[tp].tolist())}
+            src = np.array([pos[tuple(v)] for v in (-mills[t] - g0[None, :]).tolist()])
+            eps[t] = eps[tp]
+            coeffs[t] = np.conj(coeffs[tp][:, src])
+            continue
+        m = mills[t].astype(np.int64)
+        d = m[:, None, :] - m[None, :, :] + 2 * M
+        H = V[d[..., 0], d[..., 1], d[..., 2]].astype(complex)
+        q = m + k[None, :] / n_k
+        H[np.arange(len(m)), np.arange(len(m))] += 0.5 * b * b * (q * q).sum(axis=1)
+        e, U = np.linalg.eigh(H)
+        eps[t] = e[:nb]
+        coeffs[t] = U[:, :nb].T.copy()
+    return kap, mills, eps, coeffs
+
+
 def make_cell_complex(spec: CellSpec, phase_seed: int | None = None):
     """(miller, eps, coeff) from a plain complex Hermitian eigensolver.
 

@@ -141,6 +141,30 @@ def test_unrestricted_validation_paths(lib, cell):
         _setup(lib, s, m, e, c, second_spin=(e[:-1], c[:-1], 3))
 
 
+def test_kpoint_validation_paths(lib):
+    # every error of the k-point entry is found on the host
+    import dataclasses
+    from synthetic import make_cell_kmesh
+    s = dataclasses.replace(tiny_spec(seed=3, L=5.0, n=8, ecut=2.5, eaux=2.0), amp=1.0)
+    kap, mills, eps, coeffs = make_cell_kmesh(s, 2)
+
+    def mk(n_occ=1, n_k=2, e=eps, c=coeffs, m=mills, **kw):
+        return lib.Context(s.L, s.n, s.ecut, s.eaux, m, e, c, n_occ, 6, kmesh=n_k, stream=0,
+                           **kw)
+    _expect(lib, 2, lambda: mk(n_occ=3))                         # bands overlap across k
+    _expect(lib, 1, lambda: mk(n_k=0))
+    _expect(lib, 1, lambda: mk(n_occ=0))
+    e2 = eps.copy()
+    e2[3, [4, 5]] = e2[3, [5, 4]]
+    e2[3, 4] += 1e-3
+    _expect(lib, 1, lambda: mk(e=e2))                             # not ascending at one k
+    m2 = [m.copy() for m in mills]
+    m2[1][0] = m2[1][1]
+    _expect(lib, 1, lambda: mk(m=m2))                             # duplicate plane wave
+    with pytest.raises(ValueError):
+        mk(c=coeffs[:-1])
+
+
 def test_workspace_cap_enomem(lib, cell):
     s, (m, e, c) = cell
     _expect(lib, 3, lambda: _setup(lib, s, m, e, c, workspace_cap=1024))
