@@ -35,9 +35,10 @@ PEAK_FP32 = 157.3e12     # FP32 vector and matrix, FLOP/s
 PEAK_BF16 = 2.5e15       # BF16 dense matrix, FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
 
-# Sources of the pair-transform kernel; HBM traffic figures taken with
-# rocprofv3 counters are only reported while these are unchanged.
-PAIR_SOURCES = ("fft.hpp", "transforms.hpp", "kernels_fft.hpp", "grid_kernels.hip", "ltmp2.hip")
+# Sources of the pair-transform kernel (device code and its launch shapes);
+# HBM traffic figures taken with rocprofv3 counters are only reported while
+# these are unchanged.
+PAIR_SOURCES = ("fft.hpp", "transforms.hpp", "kernels_fft.hpp", "grid_kernels.hip")
 COPY_PROBE_BYTES = 1 << 30
 
 
