@@ -4,9 +4,9 @@ each restricted to a seeded, non-contiguous subset I of 16 occupied
 orbitals (two 8 x 8 blocks of occupied pairs on the library side), at the
 oracle's own minimax quadrature for the subset's denominator range.
 
-Calls only the seeded input generator and oracle/.  CPU time: minutes for
-the 32^3 cell, about an hour for the 40^3 cell (run with the cell name as
-argument to write one file).
+Calls only the seeded input generator and oracle/.  CPU time: about 40
+minutes for the 32^3 cell, several hours for the 40^3 cell (run with the
+cell name as argument to write one file).
 """
 import json
 import os
