@@ -314,8 +314,11 @@ struct PairCell {
 
 // KM >= 0: the cell's kept set is kmax = KM, known at compile time (see kwin);
 // KM = -1: runtime kmax.  JOINT: both fields side by side in two slab
-// buffers (forward_pruned_joint; shared memory fwd2_lds_bytes).
-template <class T, int N, int OPT, int NT = kThreads, int KM = -1, bool JOINT = false>
+// buffers (forward_pruned_joint; shared memory fwd2_lds_bytes).  BINS: the
+// per-shell split of the cutoff extrapolation is compiled in (taken when
+// pc.shell is set); the batched launches, which never split, leave it out.
+template <class T, int N, int OPT, int NT = kThreads, int KM = -1, bool JOINT = false,
+          bool BINS = true>
 __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void* smem,
                                  double* red) {
   const int nk = 2 * (KM >= 0 ? KM : pc.kmax) + 1;
@@ -352,7 +355,8 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
                                              L);
   double s = 0.0;
   double sb[kMaxShells] = {};
-  const int sg = pc.shell ? pc.shell[pc.g0 + gl] : 0;
+  const bool split = BINS && pc.shell;
+  const int sg = split ? pc.shell[pc.g0 + gl] : 0;
 #pragma unroll
   for (int t = 0; t < OPT; ++t) {
     const int o = threadIdx.x + t * NT;
@@ -366,17 +370,20 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
         term = 2.0 * pc.v[o] * (ar * br + ai * bi);
       }
       s += term;
-      if (pc.shell) bin_add(sb, min(int(pc.shell[o]), sg) - 1, term);
+      if constexpr (BINS)
+        if (split) bin_add(sb, min(int(pc.shell[o]), sg) - 1, term);
     }
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) pc.xpart[long(gl) * pc.npairs + p] = pc.dV2 * s;
-  if (pc.shell) {
-    __shared__ double redb[NT / 64 * kMaxShells];
-    block_sum_bins(sb, redb);
-    if (threadIdx.x == 0)
-      for (int b = 0; b < pc.nb; ++b)
-        pc.xbins[(long(gl) * pc.npairs + p) * pc.nb + b] = pc.dV2 * sb[b];
+  if constexpr (BINS) {
+    if (split) {
+      __shared__ double redb[NT / 64 * kMaxShells];
+      block_sum_bins(sb, redb);
+      if (threadIdx.x == 0)
+        for (int b = 0; b < pc.nb; ++b)
+          pc.xbins[(long(gl) * pc.npairs + p) * pc.nb + b] = pc.dV2 * sb[b];
+    }
   }
 }
 
@@ -384,7 +391,8 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
 // gets a contiguous range of the (G', pair) list, whose pairs come in 8 x 8
 // blocks of (i, j), so the workgroups resident on one XCD share a handful of
 // psi_i and w_j^{(G')} in that XCD's L2.
-template <class T, int N, int OPT, int NT = kThreads, int KM = -1, bool JOINT = false>
+template <class T, int N, int OPT, int NT = kThreads, int KM = -1, bool JOINT = false,
+          bool BINS = true>
 __global__ __launch_bounds__(NT) void k_pair(PairCell pc, int sx) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[NT / 64];
@@ -393,7 +401,8 @@ __global__ __launch_bounds__(NT) void k_pair(PairCell pc, int sx) {
   const long t = long(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= total) return;
   const int gl = int(t / pc.npairs);
-  pair_item<T, N, OPT, NT, KM, JOINT>(pc, gl, int(t - long(gl) * pc.npairs), sx, smem, red);
+  pair_item<T, N, OPT, NT, KM, JOINT, BINS>(pc, gl, int(t - long(gl) * pc.npairs), sx, smem,
+                                            red);
 }
 
 // Several cells of the same grid in one persistent launch: the work list is
@@ -420,7 +429,8 @@ __global__ __launch_bounds__(NT) void k_pair_multi(const PairCell* __restrict__ 
     const PairCell pc = cells[lo];
     const long u = t - prefix[lo];
     const int gl = int(u / pc.npairs);
-    pair_item<T, N, OPT, NT, KM>(pc, gl, int(u - long(gl) * pc.npairs), sx, smem, red);
+    pair_item<T, N, OPT, NT, KM, false, false>(pc, gl, int(u - long(gl) * pc.npairs), sx, smem,
+                                               red);
     __syncthreads();
   }
 }
