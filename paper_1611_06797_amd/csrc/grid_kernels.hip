@@ -63,10 +63,12 @@ ltmp2_status launch(K kern, dim3 grid, size_t lds, hipStream_t st, auto... args)
   return launch_nt(kern, grid, kThreads, lds, st, args...);
 }
 
-// FP32 pair transforms with more than 9 outputs per thread run 512-thread
-// workgroups with at most 9 each: the accumulators of 17 per thread would
-// leave room for only one wave per SIMD.  (FP64 registers do not fit two
-// 512-thread waves per SIMD; FP64 keeps 256 threads.)
+// FP32 pair transforms with more than 9 outputs per thread: on grids whose
+// auxiliary window allows them (n >= 30) 256-thread workgroups with up to 17
+// outputs each, held to two waves per SIMD by their launch bounds, two
+// workgroups per CU (36 grid: 118 ns per item against 135 ns for the
+// 512-thread joint form below, stand-alone timing); above 17 x 256 outputs
+// the 512-thread form with at most 9 each.  (FP64 keeps 256 threads.)
 constexpr int kWideNT = 512, kWideOpt = 9;
 // The wide form transforms both fields of an item side by side in two slab
 // buffers (forward_pruned_joint): on the 36 grid with 12-plane slabs that is
@@ -206,23 +208,32 @@ inline int pair_kfix(int kmax) {
   return (kmax == kwin(N) || (kwin(N) > 1 && kmax == kwin(N) - 1)) ? kmax : -1;
 }
 
-template <class T, int NT, int OPT, int KM, bool JOINT>
+template <class T, int NT, int OPT, int KM, bool JOINT, int MINW>
 ltmp2_status pair_go(const PairCell& pc, int sx, hipStream_t st) {
   const long total = long(pc.npairs) * pc.gb;
   const int nk = 2 * pc.kmax + 1;
-  return launch_nt(k_pair<T, N, OPT, NT, KM, JOINT>, dim3(unsigned((total + 7) / 8 * 8)), NT,
+  return launch_nt(k_pair<T, N, OPT, NT, KM, JOINT, true, MINW>,
+                   dim3(unsigned((total + 7) / 8 * 8)), NT,
                    JOINT ? fwd2_lds_bytes<T>(N, nk, sx) : fwd_lds_bytes<T>(N, nk, sx), st, pc,
                    sx);
 }
 
-template <class T, int NT, int OPT, bool JOINT = false>
+template <class T, int NT, int OPT, bool JOINT = false, int MINW = 1>
 ltmp2_status pair_km(const PairCell& pc, int sx, hipStream_t st) {
   constexpr int kw = kwin(N);
   const int kf = pair_kfix(pc.kmax);
-  if (kf == kw) return pair_go<T, NT, OPT, kw, JOINT>(pc, sx, st);
+  if (kf == kw) return pair_go<T, NT, OPT, kw, JOINT, MINW>(pc, sx, st);
   if constexpr (kw > 1)
-    if (kf == kw - 1) return pair_go<T, NT, OPT, kw - 1, JOINT>(pc, sx, st);
-  return pair_go<T, NT, OPT, -1, JOINT>(pc, sx, st);
+    if (kf == kw - 1) return pair_go<T, NT, OPT, kw - 1, JOINT, MINW>(pc, sx, st);
+  return pair_go<T, NT, OPT, -1, JOINT, MINW>(pc, sx, st);
+}
+
+// Largest slab tile d <= cap whose single slab buffer fits `limit` bytes.
+template <class T>
+int choose_sx_fwd_within(int nk, int cap, size_t limit) {
+  int sx = slab_tile_at_most(N, cap);
+  while (sx > 1 && fwd_lds_bytes<T>(N, nk, sx) > limit) sx = slab_tile_at_most(N, sx - 1);
+  return sx;
 }
 
 // Largest slab tile d <= cap whose two slab buffers (both fields of a pair
@@ -259,6 +270,21 @@ ltmp2_status pair(const T* psi, long ld, const cplx<T>* w, int no, const int* pa
   pc.g0 = g0;
   if constexpr (sizeof(T) == sizeof(float)) {
     if (ng > 9 * kThreads) {
+      // up to 17 outputs per thread: 256 threads with two waves per SIMD
+      // held by the launch bounds (244 registers, no spills on the 36 grid)
+      // and 12-plane slabs within half the shared memory, so two workgroups
+      // share a CU and overlap each other's barriers
+      // (compiled for the two fixed kept sets only: the runtime-kmax form
+      // spills at 256 registers and takes the 512-thread path instead)
+      if constexpr (kwin(N) >= 9) {
+        constexpr int kw = kwin(N);
+        const int kf = pair_kfix(kmax);
+        const int sx = choose_sx_fwd_within<T>(2 * kmax + 1, 12, kLdsHalf);
+        if (ng <= 17 * kThreads && kf == kw)
+          return pair_go<T, kThreads, 17, kw, false, 2>(pc, sx, st);
+        if (ng <= 17 * kThreads && kf == kw - 1)
+          return pair_go<T, kThreads, 17, kw - 1, false, 2>(pc, sx, st);
+      }
       if (ng > kWideOpt * kWideNT) return LTMP2_EINVAL;
       return pair_km<T, kWideNT, kWideOpt, true>(pc, choose_sx_joint<T>(2 * kmax + 1, 12), st);
     }

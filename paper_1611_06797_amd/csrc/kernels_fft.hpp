@@ -392,8 +392,8 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
 // blocks of (i, j), so the workgroups resident on one XCD share a handful of
 // psi_i and w_j^{(G')} in that XCD's L2.
 template <class T, int N, int OPT, int NT = kThreads, int KM = -1, bool JOINT = false,
-          bool BINS = true>
-__global__ __launch_bounds__(NT) void k_pair(PairCell pc, int sx) {
+          bool BINS = true, int MINW = 1>
+__global__ __launch_bounds__(NT, MINW) void k_pair(PairCell pc, int sx) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[NT / 64];
   const long total = long(pc.npairs) * pc.gb;
