@@ -264,6 +264,41 @@ def test_c3_occupied_subset_vs_oracle(torch_cuda):
             assert np.allclose(pt[:, 1], ref["per_tau_x"], rtol=1e-9, atol=0)
 
 
+def test_c3_subset_cutoff_extrapolation_paths(torch_cuda):
+    # the per-shell split on the 36^3 pair forms (FP64: 256 threads x 17
+    # outputs; FP32 and BF16x3: the two-per-CU 17-output form): the first
+    # cutoff is the plain energy (stored oracle value for FP64), every
+    # cutoff's energy agrees between the precision forms, and the nested
+    # energies shrink in magnitude with the cutoff
+    import json
+    import os
+    from synthetic import C3
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3_subset.json")) as f:
+        ref = json.load(f)
+    m, e, c = make_cell(C3)
+    occ = np.array(ref["occ"])
+    tau, w = np.array(ref["tau"]), np.array(ref["w"])
+    sel = np.concatenate([occ, np.arange(C3.n_occ, len(e))])
+    sub = CellSpec(L=C3.L, n=C3.n, ecut=C3.ecut, eaux=C3.eaux, n_occ=len(occ),
+                   n_tau=C3.n_tau, seed=C3.seed)
+    out = {}
+    for prec in (0, 1, 2):
+        _say("C3 subset cutoff extrapolation, prec", prec)
+        with _ctx(sub, m, e[sel], c[sel], tau=tau, w=w, prec=prec, n_extrap=8) as ctx:
+            ed, ex, pt, qe = ctx.energy()
+            ea, edn, exn, einf = ctx.extrapolation(8)
+        out[prec] = (edn, exn)
+        assert abs(edn[0] - ed) <= 1e-12 * abs(ed) and abs(exn[0] - ex) <= 1e-12 * abs(ex)
+        assert np.all(np.diff(np.abs(edn)) < 0)
+        print(f"[c3 extrap prec={prec}] E_d[n]={np.round(edn, 8).tolist()} E_inf={einf[0]:.8f}",
+              flush=True)
+    assert abs(out[0][0][0] - ref["e_d_lt"]) <= 1e-9 * abs(ref["e_d_lt"])
+    assert abs(out[0][1][0] - ref["e_x_lt"]) <= 1e-9 * abs(ref["e_x_lt"])
+    for prec in (1, 2):
+        assert np.abs(out[prec][0] - out[0][0]).max() < len(occ) * 1e-6
+        assert np.abs(out[prec][1] - out[0][1]).max() < len(occ) * 1e-6
+
+
 @pytest.mark.parametrize("prec", [0, 2])
 def test_c1_phased_inputs(torch_cuda, prec):
     # orbitals from a plain complex eigensolver with seeded random phases:
