@@ -67,6 +67,28 @@ def test_tiny_mesh_vs_oracle(torch_cuda, n_k, n_occ):
     assert np.allclose(pt[:, 1], ref["per_tau_x"], rtol=1e-9, atol=0)
 
 
+def test_tiny_mesh_per_tau_entry_points(torch_cuda):
+    # ltmp2_chi, ltmp2_exchange and ltmp2_direct_hartree return per-cell
+    # values that match ltmp2_energy's per-tau terms
+    from oracle.kpoints import KProblem
+    from oracle.quadrature import minimax_laplace
+    s = _tiny()
+    n_k, n_occ = 2, 1
+    kap, mills, eps, coeffs = make_cell_kmesh(s, n_k)
+    K = KProblem(s.L, s.n, s.eaux, n_k, kap, mills, eps, coeffs, n_occ)
+    tau, w, _ = minimax_laplace(*K.x_range(), 6)
+    _say("tiny cell, k mesh 2, per-tau entry points")
+    with _kctx(s, n_k, mills, eps, coeffs, n_occ, tau, w) as ctx:
+        ed, ex, pt, qe = ctx.energy()
+        for t in (0, 3, 5):
+            d_chi = ctx.chi(t)
+            d_h = ctx.direct_hartree(t)
+            x = ctx.exchange(t)
+            assert abs(d_chi - pt[t, 0]) <= 1e-12 * abs(pt[t, 0])
+            assert abs(d_h - pt[t, 0]) <= 1e-10 * abs(pt[t, 0])
+            assert abs(x - pt[t, 1]) <= 1e-12 * abs(pt[t, 1])
+
+
 def test_single_point_mesh_equals_gamma_context(torch_cuda):
     from paper_1611_06797_amd import Context
     from oracle.quadrature import minimax_laplace
