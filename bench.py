@@ -346,8 +346,8 @@ def main():
                     help="directory for the generated cell arrays (reused when present)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs the LTMP2 path on one GPU only (no sharded "
-                                   "form is built); run with --gpus 1"}))
+        print(json.dumps({"error": "the library runs the LTMP2 path on one GPU (there is no "
+                                   "sharded form); run with --gpus 1"}))
         sys.exit(2)
 
     if args.config == "c4":
