@@ -299,6 +299,34 @@ def test_c3_subset_cutoff_extrapolation_paths(torch_cuda):
         assert np.abs(out[prec][1] - out[0][1]).max() < len(occ) * 1e-6
 
 
+def test_c3_runtime_kept_set_forms(torch_cuda):
+    # an auxiliary cutoff whose kept set (k_max 9) is neither of the two
+    # compiled windows of the 36^3 grid, with more than 9 x 256 vectors: the
+    # FP32 and BF16x3 pair transforms take the 512-thread two-field form and
+    # the FP64 ones the 256-thread runtime form; the three agree to the
+    # mixed-precision bar, and the FP64 energy is real and negative / positive
+    from synthetic import C3
+    m, e, c = make_cell(C3)
+    occ = np.array([150, 153, 157, 159])
+    sel = np.concatenate([occ, np.arange(C3.n_occ, len(e))])
+    sub = CellSpec(L=C3.L, n=C3.n, ecut=C3.ecut, eaux=4.5, n_occ=len(occ), n_tau=6,
+                   seed=C3.seed)
+    res = {}
+    for prec in (0, 1, 2):
+        _say("C3 subset, runtime kept set, prec", prec)
+        with _ctx(sub, m, e[sel], c[sel], prec=prec) as ctx:
+            info = ctx.info
+            res[prec] = ctx.energy()
+        assert info.n_grid == 36 and info.n_g > 9 * 256
+    ed0, ex0 = res[0][0], res[0][1]
+    assert ed0 < 0 < ex0
+    for prec in (1, 2):
+        print(f"[c3 runtime kmax prec={prec}] dE_d={res[prec][0] - ed0:.3e} "
+              f"dE_x={res[prec][1] - ex0:.3e}", flush=True)
+        assert abs(res[prec][0] - ed0) < len(occ) * 1e-6
+        assert abs(res[prec][1] - ex0) < len(occ) * 1e-6
+
+
 @pytest.mark.parametrize("prec", [0, 2])
 def test_c1_phased_inputs(torch_cuda, prec):
     # orbitals from a plain complex eigensolver with seeded random phases:
