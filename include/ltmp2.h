@@ -1,12 +1,15 @@
 /*
- * libltmp2 -- Gamma-only Laplace-transformed MP2 (LTMP2) on one MI355X.
+ * libltmp2 -- Laplace-transformed MP2 (LTMP2) for periodic cells on one MI355X.
  *
  * C ABI over the hot path of the quartic-scaling plane-wave LTMP2 method of
  * Schaefer, Ramberger and Kresse ("Quartic scaling MP2 for solids",
  * arXiv:1611.06797).  Given Hartree-Fock orbitals and energies for all
  * occupied and virtual states (the inputs the paper's Implementation section
  * assumes), the library returns the direct and exchange MP2 correlation
- * energies of a spin-restricted closed-shell cell:
+ * energies of a cell: spin-restricted at the Gamma point (ltmp2_setup),
+ * spin-unrestricted (ltmp2_setup_unrestricted) or on a k-point mesh
+ * (ltmp2_setup_kpoints), optionally with the internal extrapolation of the
+ * auxiliary cutoff.  For the spin-restricted Gamma-point cell:
  *
  *   E_d = -2 sum_n w_n Tr[(chi(tau_n) v)^2]                (Eq. dLTMP2Compact, q = 0)
  *   E_x =    sum_n w_n sum_{G,G'} v(G) v(G') sum_ij A^{G'}_ij(G) A^{-G'}_ji(-G)
