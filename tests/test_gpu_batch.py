@@ -122,6 +122,37 @@ def test_batch_library_quadrature(mix):
         assert abs(ed[k] - e1) < 1e-9 and abs(ex[k] - x1) < 1e-9, k
 
 
+def test_batch_wide_auxiliary_sets(mix):
+    # cells whose auxiliary sets exceed 9 x 256 vectors (32^3 internal grid):
+    # the fused launch takes the 512-thread batched form; every cell agrees
+    # with its own single-cell context (256-thread 17-output form) and with
+    # the FP64 single-cell path
+    from paper_1611_06797_amd import Batch, Context, FP32, FP64
+    specs = [CellSpec(L=20.0, n=40, ecut=5.0, eaux=5.0, n_occ=3, n_tau=4, seed=7),
+             CellSpec(L=20.0, n=40, ecut=5.0, eaux=5.0, n_occ=2, n_tau=5, seed=8)]
+    items = []
+    for s in specs:
+        m, e, c = make_cell(s)
+        items.append(dict(spec=s, m=m, e=e, c=c, tau=None, w=None))
+    _say("batch fp32, two cells with wide auxiliary sets")
+    with Batch(_cells(items, given=False), prec=FP32) as b:
+        ed, ex = b.energy()
+        infos = [b.cell_info(k) for k in range(len(items))]
+    for k, it in enumerate(items):
+        s = it["spec"]
+        assert infos[k].n_g > 9 * 256 and infos[k].n_grid == 32
+        with Context(s.L, s.n, s.ecut, s.eaux, it["m"], it["e"], it["c"], s.n_occ, s.n_tau,
+                     prec=FP32) as ctx:
+            e1, x1, _, _ = ctx.energy()
+        with Context(s.L, s.n, s.ecut, s.eaux, it["m"], it["e"], it["c"], s.n_occ, s.n_tau,
+                     prec=FP64) as ctx:
+            e0, x0, _, _ = ctx.energy()
+        print(f"[batch wide cell {k}] n_g={infos[k].n_g} dE_d(batch-single)={ed[k] - e1:.3e} "
+              f"dE_d(batch-fp64)={ed[k] - e0:.3e} dE_x(batch-fp64)={ex[k] - x0:.3e}", flush=True)
+        assert abs(ed[k] - e1) < 1e-7 * abs(e1) + 1e-9 and abs(ex[k] - x1) < 1e-7 * abs(x1) + 1e-9
+        assert abs(ed[k] - e0) < s.n_occ * 1e-6 and abs(ex[k] - x0) < s.n_occ * 1e-6
+
+
 def test_batch_rejects_mixed_precision_cells(mix):
     import ctypes as C
     from paper_1611_06797_amd import Batch, FP64, LTMP2Error
