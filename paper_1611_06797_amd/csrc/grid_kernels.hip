@@ -292,10 +292,10 @@ ltmp2_status pair(const T* psi, long ld, const cplx<T>* w, int no, const int* pa
   return by_opt<PairF<T>::template F>(ng, pc, choose_sx_fwd<T>(2 * kmax + 1), st);
 }
 
-template <class T, int NT, int OPT, int KM>
+template <class T, int NT, int OPT, int KM, int MINW = 1>
 ltmp2_status pair_multi_go(const PairCell* cells, const long* prefix, int ncells, int kmax_max,
                            int sx, int nblocks, hipStream_t st) {
-  return launch_nt(k_pair_multi<T, N, OPT, NT, KM>, dim3(unsigned(nblocks)), NT,
+  return launch_nt(k_pair_multi<T, N, OPT, NT, KM, MINW>, dim3(unsigned(nblocks)), NT,
                    fwd_lds_bytes<T>(N, 2 * kmax_max + 1, sx), st, cells, prefix, ncells, sx);
 }
 
@@ -335,7 +335,21 @@ ltmp2_status pair_multi(const PairCell* cells, const long* prefix, int ncells, i
                         int kmax_max, int kfix, int sx, int nblocks, hipStream_t st) {
   if constexpr (sizeof(T) == sizeof(float)) {
     if (ng_max > 9 * kThreads) {
-      if (ng_max > kWideOpt * kWideNT || sx < 1 || N % sx != 0 || sx > 12) return LTMP2_EINVAL;
+      if (sx < 1 || N % sx != 0 || sx > 12) return LTMP2_EINVAL;
+      // the single-cell wide form: 256 threads, up to 17 outputs, two
+      // workgroups per CU when the slab fits half the shared memory
+      if constexpr (kwin(N) >= 9) {
+        constexpr int kw = kwin(N);
+        if (ng_max <= 17 * kThreads && fwd_lds_bytes<T>(N, 2 * kmax_max + 1, sx) <= kLdsHalf) {
+          if (kfix == kw)
+            return pair_multi_go<T, kThreads, 17, kw, 2>(cells, prefix, ncells, kmax_max, sx,
+                                                         nblocks, st);
+          if (kfix == kw - 1)
+            return pair_multi_go<T, kThreads, 17, kw - 1, 2>(cells, prefix, ncells, kmax_max,
+                                                             sx, nblocks, st);
+        }
+      }
+      if (ng_max > kWideOpt * kWideNT) return LTMP2_EINVAL;
       return pair_multi_km<T, kWideNT, kWideOpt>(kfix, cells, prefix, ncells, kmax_max, sx,
                                                   nblocks, st);
     }

@@ -409,8 +409,8 @@ __global__ __launch_bounds__(NT, MINW) void k_pair(PairCell pc, int sx) {
 // the concatenation of every cell's (G', pair) items (prefix[c] = first item
 // of cell c); each XCD owns a contiguous range and its workgroups stride
 // through it, so every workgroup exits after a bounded number of items.
-template <class T, int N, int OPT, int NT = kThreads, int KM = -1>
-__global__ __launch_bounds__(NT) void k_pair_multi(const PairCell* __restrict__ cells,
+template <class T, int N, int OPT, int NT = kThreads, int KM = -1, int MINW = 1>
+__global__ __launch_bounds__(NT, MINW) void k_pair_multi(const PairCell* __restrict__ cells,
                                                          const long* __restrict__ prefix,
                                                          int ncells, int sx) {
   extern __shared__ __align__(16) char smem[];

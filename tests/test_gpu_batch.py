@@ -124,8 +124,8 @@ def test_batch_library_quadrature(mix):
 
 def test_batch_wide_auxiliary_sets(mix):
     # cells whose auxiliary sets exceed 9 x 256 vectors (32^3 internal grid):
-    # the fused launch takes the 512-thread batched form; every cell agrees
-    # with its own single-cell context (256-thread 17-output form) and with
+    # the fused launch takes the wide batched form; every cell agrees
+    # with its own single-cell context (the same 17-output form) and with
     # the FP64 single-cell path
     from paper_1611_06797_amd import Batch, Context, FP32, FP64
     specs = [CellSpec(L=20.0, n=40, ecut=5.0, eaux=5.0, n_occ=3, n_tau=4, seed=7),
