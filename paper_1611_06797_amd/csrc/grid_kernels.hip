@@ -208,14 +208,18 @@ inline int pair_kfix(int kmax) {
   return (kmax == kwin(N) || (kwin(N) > 1 && kmax == kwin(N) - 1)) ? kmax : -1;
 }
 
+// Launches that split by cutoff shell run an instance with that epilogue
+// compiled in; the others run one without it (fewer live registers, and its
+// z lines are read through buffer resources).
 template <class T, int NT, int OPT, int KM, bool JOINT, int MINW>
 ltmp2_status pair_go(const PairCell& pc, int sx, hipStream_t st) {
   const long total = long(pc.npairs) * pc.gb;
   const int nk = 2 * pc.kmax + 1;
-  return launch_nt(k_pair<T, N, OPT, NT, KM, JOINT, true, MINW>,
-                   dim3(unsigned((total + 7) / 8 * 8)), NT,
-                   JOINT ? fwd2_lds_bytes<T>(N, nk, sx) : fwd_lds_bytes<T>(N, nk, sx), st, pc,
-                   sx);
+  const dim3 grid(unsigned((total + 7) / 8 * 8));
+  const size_t lds = JOINT ? fwd2_lds_bytes<T>(N, nk, sx) : fwd_lds_bytes<T>(N, nk, sx);
+  if (pc.shell)
+    return launch_nt(k_pair<T, N, OPT, NT, KM, JOINT, true, MINW>, grid, NT, lds, st, pc, sx);
+  return launch_nt(k_pair<T, N, OPT, NT, KM, JOINT, false, MINW>, grid, NT, lds, st, pc, sx);
 }
 
 template <class T, int NT, int OPT, bool JOINT = false, int MINW = 1>

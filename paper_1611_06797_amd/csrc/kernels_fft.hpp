@@ -293,6 +293,54 @@ __global__ __launch_bounds__(kThreads) void k_wstates(const T* __restrict__ P, i
 // Summed over pairs this is S_x(G') = sum_G v(G) sum_ij A_ij(G) A^{(-G')}_ji(-G),
 // using A^{(-G')}_ji(-G) = conj A^{(G')}_ji(G) for real orbitals.
 
+// The pair item's rows are the same for every lane of the workgroup; taking
+// a row's address from the first lane tells the compiler so, and lets it
+// address the z line as scalar base + 32-bit lane offset + the step along z
+// folded into the load instruction, with no per-load 64-bit arithmetic.
+template <class V>
+using global_row = const __attribute__((address_space(1))) V*;
+template <class V>
+__device__ inline global_row<V> uniform_row(const V* p) {
+  const unsigned long long u = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(u));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(u >> 32));
+  return reinterpret_cast<global_row<V>>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// The same rows through buffer resources: the base in scalar registers, a
+// 32-bit lane offset, the step along z in the instruction, no address
+// arithmetic at all.  Word 3 holds the gfx9-family default format;
+// num_records bounds every access to the row (reads past it return zero).
+// Used where the compiler keeps a whole z line of these loads in flight
+// (the forms without the per-shell epilogue or a second slab buffer); with
+// more live registers it spaces them out, and global loads then do better.
+template <class V>
+__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const V* p, unsigned n) {
+  const unsigned long long u = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(u));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(u >> 32));
+  void* q = reinterpret_cast<void*>((static_cast<unsigned long long>(hi) << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, short(0), int(n * sizeof(V)), 0x00020000);
+}
+template <class V>
+__device__ inline V row_load(__amdgpu_buffer_rsrc_t rs, unsigned off);
+template <>
+__device__ inline float row_load<float>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+template <>
+__device__ inline double row_load<double>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+}
+template <>
+__device__ inline cplx<float> row_load<cplx<float>>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+}
+template <>
+__device__ inline cplx<double> row_load<cplx<double>>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  return __builtin_bit_cast(cplx<double>, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+}
+
 // Everything one cell contributes to a pair launch.
 struct PairCell {
   const void* psi;     // [nocc..][ld] orbitals (T)
@@ -331,6 +379,8 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
   const T* pj = psi + long(j) * pc.ld;
   const cplx<T>* wi = w + (long(gl) * pc.nocc + i) * pc.ld;
   const cplx<T>* wj = w + (long(gl) * pc.nocc + j) * pc.ld;
+  constexpr unsigned nr = unsigned(N) * N * N;
+  constexpr bool kBuffer = !JOINT && !BINS;
   int gd[OPT];
   cplx<T> acc[2][OPT];
 #pragma unroll
@@ -341,11 +391,23 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
     acc[1][t] = {T(0), T(0)};
   }
   __syncthreads();
+  // r = (x N + z) N + y: the lane's line start, then the step z N
+  const auto gpi = uniform_row(pi), gpj = uniform_row(pj);
+  const auto gwi = uniform_row(wi), gwj = uniform_row(wj);
+  const auto bpi = row_rsrc(pi, nr), bpj = row_rsrc(pj, nr);
+  const auto bwi = row_rsrc(wi, nr), bwj = row_rsrc(wj, nr);
   auto ld_ = [&](int f, int x, int y, int z) {
-    const long r = (x * N + z) * N + y;
-    const T a = (f == 0) ? pi[r] : pj[r];
-    const cplx<T> b = (f == 0) ? wj[r] : wi[r];
-    return cplx<T>{a * b.x, a * b.y};
+    const unsigned r0 = unsigned(x * N * N + y);
+    if constexpr (kBuffer) {
+      const unsigned r = r0 + unsigned(z * N);
+      const T a = row_load<T>(f == 0 ? bpi : bpj, r * unsigned(sizeof(T)));
+      const cplx<T> b = row_load<cplx<T>>(f == 0 ? bwj : bwi, r * unsigned(sizeof(cplx<T>)));
+      return cplx<T>{a * b.x, a * b.y};
+    } else {
+      const T a = ((f == 0) ? gpi : gpj)[size_t(r0) + z * N];
+      const auto& b = ((f == 0) ? gwj : gwi)[size_t(r0) + z * N];
+      return cplx<T>{a * b.x, a * b.y};
+    }
   };
   if constexpr (JOINT)
     forward_pruned_joint<T, -1, N, OPT, NT, KM>(ld_, (i == j) ? 1 : 2, pc.kmax, sx, gd, pc.ng, acc,
