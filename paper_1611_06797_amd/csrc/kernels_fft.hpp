@@ -311,9 +311,10 @@ __device__ inline global_row<V> uniform_row(const V* p) {
 // 32-bit lane offset, the step along z in the instruction, no address
 // arithmetic at all.  Word 3 holds the gfx9-family default format;
 // num_records bounds every access to the row (reads past it return zero).
-// Used where the compiler keeps a whole z line of these loads in flight
-// (the forms without the per-shell epilogue or a second slab buffer); with
-// more live registers it spaces them out, and global loads then do better.
+// Used for FP32 where the compiler keeps a whole z line of these loads in
+// flight (the forms without the per-shell epilogue or a second slab
+// buffer); with more live registers it spaces them out, and the global
+// loads above then do better.
 template <class V>
 __device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const V* p, unsigned n) {
   const unsigned long long u = reinterpret_cast<unsigned long long>(p);
@@ -329,16 +330,8 @@ __device__ inline float row_load<float>(__amdgpu_buffer_rsrc_t rs, unsigned off)
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
 }
 template <>
-__device__ inline double row_load<double>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
-}
-template <>
 __device__ inline cplx<float> row_load<cplx<float>>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
   return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
-}
-template <>
-__device__ inline cplx<double> row_load<cplx<double>>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
-  return __builtin_bit_cast(cplx<double>, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
 }
 
 // Everything one cell contributes to a pair launch.
@@ -380,7 +373,11 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
   const cplx<T>* wi = w + (long(gl) * pc.nocc + i) * pc.ld;
   const cplx<T>* wj = w + (long(gl) * pc.nocc + j) * pc.ld;
   constexpr unsigned nr = unsigned(N) * N * N;
-  constexpr bool kBuffer = !JOINT && !BINS;
+  // FP32: buffer loads where the whole line stays in flight, else scalar-base
+  // global loads; FP64 (twice the registers per value) keeps plain 64-bit
+  // addresses, which the compiler schedules best there
+  constexpr bool kFp32 = sizeof(T) == sizeof(float);
+  constexpr bool kBuffer = kFp32 && !JOINT && !BINS;
   int gd[OPT];
   cplx<T> acc[2][OPT];
 #pragma unroll
@@ -391,11 +388,11 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
     acc[1][t] = {T(0), T(0)};
   }
   __syncthreads();
-  // r = (x N + z) N + y: the lane's line start, then the step z N
   const auto gpi = uniform_row(pi), gpj = uniform_row(pj);
   const auto gwi = uniform_row(wi), gwj = uniform_row(wj);
   const auto bpi = row_rsrc(pi, nr), bpj = row_rsrc(pj, nr);
   const auto bwi = row_rsrc(wi, nr), bwj = row_rsrc(wj, nr);
+  // grid index r = (x N + z) N + y: the lane's line start r0, then z N
   auto ld_ = [&](int f, int x, int y, int z) {
     const unsigned r0 = unsigned(x * N * N + y);
     if constexpr (kBuffer) {
@@ -403,9 +400,14 @@ __device__ inline void pair_item(const PairCell& pc, int gl, int p, int sx, void
       const T a = row_load<T>(f == 0 ? bpi : bpj, r * unsigned(sizeof(T)));
       const cplx<T> b = row_load<cplx<T>>(f == 0 ? bwj : bwi, r * unsigned(sizeof(cplx<T>)));
       return cplx<T>{a * b.x, a * b.y};
-    } else {
+    } else if constexpr (kFp32) {
       const T a = ((f == 0) ? gpi : gpj)[size_t(r0) + z * N];
       const auto& b = ((f == 0) ? gwj : gwi)[size_t(r0) + z * N];
+      return cplx<T>{a * b.x, a * b.y};
+    } else {
+      const long r = (x * N + z) * N + y;
+      const T a = (f == 0) ? pi[r] : pj[r];
+      const cplx<T> b = (f == 0) ? wj[r] : wi[r];
       return cplx<T>{a * b.x, a * b.y};
     }
   };
