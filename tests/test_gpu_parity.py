@@ -269,7 +269,11 @@ def test_c3_subset_cutoff_extrapolation_paths(torch_cuda):
     # outputs; FP32 and BF16x3: the two-per-CU 17-output form): the first
     # cutoff is the plain energy (stored oracle value for FP64), every
     # cutoff's energy agrees between the precision forms, and the nested
-    # energies shrink in magnitude with the cutoff
+    # energies shrink in magnitude with the cutoff.  A context without the
+    # split runs the pair instance without that epilogue (FP32: z lines read
+    # through buffer resources instead of global loads): the same sums, up
+    # to FP32 rounding where the two compiled instances fuse operations
+    # differently (measured 1e-10 relative; bar 1e-8)
     import json
     import os
     from synthetic import C3
@@ -289,6 +293,12 @@ def test_c3_subset_cutoff_extrapolation_paths(torch_cuda):
             ea, edn, exn, einf = ctx.extrapolation(8)
         out[prec] = (edn, exn)
         assert abs(edn[0] - ed) <= 1e-12 * abs(ed) and abs(exn[0] - ex) <= 1e-12 * abs(ex)
+        with _ctx(sub, m, e[sel], c[sel], tau=tau, w=w, prec=prec) as ctx:
+            ed0, ex0, _, _ = ctx.energy()
+        print(f"[c3 extrap prec={prec}] split - plain: dE_d={ed - ed0:.3e} dE_x={ex - ex0:.3e}",
+              flush=True)
+        rel = 1e-12 if prec == 0 else 1e-8
+        assert abs(ed0 - ed) <= rel * abs(ed) and abs(ex0 - ex) <= rel * abs(ex)
         assert np.all(np.diff(np.abs(edn)) < 0)
         print(f"[c3 extrap prec={prec}] E_d[n]={np.round(edn, 8).tolist()} E_inf={einf[0]:.8f}",
               flush=True)
