@@ -209,8 +209,8 @@ inline int pair_kfix(int kmax) {
 }
 
 // Launches that split by cutoff shell run an instance with that epilogue
-// compiled in; the others run one without it (fewer live registers, and its
-// z lines are read through buffer resources).
+// compiled in; the others run one without it (fewer live registers; in FP32
+// single-buffer forms its z lines are read through buffer resources).
 template <class T, int NT, int OPT, int KM, bool JOINT, int MINW>
 ltmp2_status pair_go(const PairCell& pc, int sx, hipStream_t st) {
   const long total = long(pc.npairs) * pc.gb;
